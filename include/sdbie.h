@@ -1,0 +1,183 @@
+/*
+ * sdbie: regularised boundary-integral Stokes-Darcy solver for one GPU (gfx950).
+ *
+ * C ABI.  Every pointer argument named as device memory must point to memory
+ * on the current HIP device (for example a torch tensor's data); every
+ * floating-point array is IEEE double, contiguous, and vector fields are
+ * component-major "SoA": element (c, j) of a 3-vector field lives at
+ * v[c * n + j].  `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  All work is enqueued on that stream; outputs are valid once the
+ * stream has reached the end of the call (the caller synchronises).  Solves
+ * synchronise the stream internally (the Krylov least-squares step runs on
+ * the host) and return only after their outputs are written.
+ *
+ * Ownership: the library never allocates or frees device memory.  The caller
+ * passes a workspace of sdbie_workspace_bytes() bytes to sdbie_plan_create();
+ * a plan refers to that workspace (and copies the node data into it) until
+ * sdbie_plan_destroy().  Calls on one plan must not overlap in time; plans
+ * with separate workspaces are independent.
+ *
+ * Errors: every function returns an int status.  0 = SDBIE_OK; 1 =
+ * SDBIE_NOT_CONVERGED (outputs hold the last iterate, `info` is filled);
+ * negative values are errors and leave outputs unspecified.  A message for
+ * the last error of the calling thread is returned by sdbie_last_error().
+ * No C++ exception crosses this interface.
+ *
+ * Paper: S. Tlupova, "A domain decomposition solution of the Stokes-Darcy
+ * system in 3D based on boundary integrals" (arXiv 2110.10749).
+ */
+#ifndef SDBIE_H
+#define SDBIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SDBIE_OK 0
+#define SDBIE_NOT_CONVERGED 1
+#define SDBIE_ERR_ARG (-1)       /* invalid argument (null pointer, size, parameter range) */
+#define SDBIE_ERR_NONFINITE (-2) /* NaN or Inf in the node data or in an iterate */
+#define SDBIE_ERR_DEVICE (-3)    /* a HIP call or kernel launch failed */
+#define SDBIE_ERR_WORKSPACE (-4) /* workspace missing, too small or misaligned */
+
+/* Arithmetic of the pair sums.  SDBIE_FP64: every pair in double.
+ * SDBIE_MIXED: pair geometry, smoothing and kernel values in float,
+ * per-tile partial sums added into double accumulators per target; solves
+ * recover double accuracy by iterative refinement with double residuals. */
+typedef enum { SDBIE_FP64 = 0, SDBIE_MIXED = 1 } sdbie_precision;
+
+/* Which layer sum (section "High-order regularization of kernels on the
+ * surface"; every sum includes j = i with the finite rho -> 0 limits):
+ *   SDBIE_SL     single layer:  Laplace  S_L[g]_i = -(1/4pi) sum_j w_j g_j s1(r/d)/r
+ *                               Stokes   V[f]_i   = (1/(8 pi mu)) sum_j w_j [f_j s1/r + D (D.f_j) s3/r^3]
+ *   SDBIE_DL_RAW double layer:  Laplace  D_L[p]_i = -(1/4pi) sum_j w_j p_j (D.n_j) s2/r^3
+ *                               Stokes   D_S[u]_i = -(3/4pi) sum_j w_j (u_j.D)(D.n_j) D s4/r^5
+ *   SDBIE_DL_SUB double layer with the singularity subtracted, eqs. (H_subtr) and (K_subtr):
+ *                               Laplace  A_D[p]_i = (1/4pi) sum_j w_j (p_j-p_i)(D.n_j) s2/r^3  (= p/2 - H p)
+ *                               Stokes   A_S[u]_i = u_i - (3/4pi) sum_j w_j ((u_j-u_i).D)(D.n_j) D s4/r^5 (= u/2 - K u)
+ * with D = x_i - x_j, r = |D|, d = delta and the smoothing functions s1..s4
+ * of the paper.  No completion term is added by the layer applies. */
+typedef enum { SDBIE_SL = 0, SDBIE_DL_RAW = 1, SDBIE_DL_SUB = 2 } sdbie_layer;
+
+/* Node set of a closed surface (section "Quadrature", eq. (Quadrature)):
+ * points x, unit normals nrm pointing out of the porous body into the fluid,
+ * quadrature weights w >= 0 (device memory, [3][n], [3][n], [n]), and the
+ * regularisation width delta > 0 (the paper uses delta = 3h). */
+typedef struct {
+    int64_t n;
+    const double* x;
+    const double* nrm;
+    const double* w;
+    double delta;
+} sdbie_surface;
+
+/* Physical parameters: viscosity mu > 0, permeability K > 0 (the paper's
+ * kappa), slip coefficient alpha >= 0 (the paper's gamma); the slip
+ * traction is beta * (u - (u.n) n) with beta = alpha * mu / sqrt(K). */
+typedef struct {
+    double mu;
+    double K;
+    double alpha;
+} sdbie_params;
+
+typedef struct {
+    double tol_gmres;   /* local solves: stop at ||r||_2 <= tol ||b||_2 */
+    double tol_ddm;     /* interface loop: residual of eq. (DDM_residual) (relaxation) or
+                           relative GMRES residual of the interface equation (outer = 1) */
+    double theta;       /* relaxation parameter of eq. (q_update), 0 < theta < 1 */
+    int maxit_gmres;    /* per local solve */
+    int restart;        /* GMRES restart length, 1 <= restart <= the plan's max_restart */
+    int maxit_ddm;      /* interface iterations (relaxation) or outer GMRES iterations */
+    int outer;          /* 0: relaxation (section "Algorithm"); 1: GMRES on the interface unknown */
+    int slip;           /* 0: slip traction implicit in the Stokes solve; 1: lagged by one
+                           interface iteration as printed in the algorithm */
+    int prec;           /* sdbie_precision of the pair sums in the solves */
+    double tol_mixed;   /* SDBIE_MIXED: relative tolerance of each float-pair correction solve */
+    int refine_max;     /* SDBIE_MIXED: maximum refinement steps */
+} sdbie_opts;
+
+typedef struct {
+    int ddm_iters;          /* interface iterations (relaxation) or outer GMRES iterations */
+    int gmres_iters;        /* inner GMRES iterations, all local solves */
+    int refine_steps;       /* SDBIE_MIXED refinement steps */
+    int64_t applies_fp64;   /* layer-sum kernel passes, double pairs */
+    int64_t applies_mixed;  /* layer-sum kernel passes, float pairs */
+    double pairs;           /* (target, source) pair evaluations, all passes */
+    double ddm_res;         /* final interface residual */
+    double relres;          /* final relative residual of the last local solve */
+} sdbie_info;
+
+typedef struct sdbie_plan_s* sdbie_plan;
+
+/* Fill `o` with the defaults: tol_gmres 1e-10, tol_ddm 1e-8, theta 0.5,
+ * maxit_gmres 500, restart 50, maxit_ddm 200, outer 1, slip 0, prec FP64,
+ * tol_mixed 1e-5, refine_max 8. */
+void sdbie_default_opts(sdbie_opts* o);
+
+/* Bytes of device workspace a plan for n nodes and GMRES restart length up
+ * to max_restart needs (0 if the arguments are invalid). */
+size_t sdbie_workspace_bytes(int64_t n, int max_restart);
+
+/* Stage a surface: spatial (Morton) ordering, double and float copies of the
+ * node data, tile bounds.  `ws` (device, 256-byte aligned, ws_bytes >=
+ * sdbie_workspace_bytes(s->n, max_restart)) must stay valid until the plan is
+ * destroyed; the node arrays of `s` are copied and may be freed afterwards.
+ * Synchronises `stream`.  Errors: ERR_ARG, ERR_WORKSPACE, ERR_NONFINITE
+ * (non-finite node data or weights), ERR_DEVICE. */
+int sdbie_plan_create(sdbie_plan* plan, const sdbie_surface* s, int max_restart,
+                      void* ws, size_t ws_bytes, void* stream);
+int sdbie_plan_destroy(sdbie_plan plan);
+int64_t sdbie_plan_n(sdbie_plan plan);
+
+/* out = layer sum of `dens` (device, [n] for Laplace, [3][n] for Stokes, in
+ * the caller's node order) at every node.  out must not alias dens.
+ * Stokes single layer uses viscosity mu > 0 (ignored by the double layers). */
+int laplace_layer_apply(sdbie_plan plan, sdbie_layer layer, const double* dens, double* out,
+                        sdbie_precision prec, void* stream);
+int stokes_layer_apply(sdbie_plan plan, double mu, sdbie_layer layer, const double* dens,
+                       double* out, sdbie_precision prec, void* stream);
+
+/* Darcy problem, eq. (Darcy_final): given v = u.n on the nodes (device [n]),
+ * solve (1/2 - H) p = b_D with b_D = -L dp/dn, dp/dn = -(mu/K) v, as
+ * (A_D + w^T p/|S|) p = -S_L[dp/dn] by GMRES (the rank-one term fixes the
+ * constant null vector of A_D), then remove the weighted mean of p.
+ * p (device [n]) holds the initial guess on entry (zero it for none). */
+int darcy_solve(sdbie_plan plan, const sdbie_params* prm, const double* vn, double* p,
+                const sdbie_opts* opts, sdbie_info* info, void* stream);
+
+/* Stokes problem, eq. (Stokes_final), with traction eq. (f) read as
+ * f = -p n + beta (u - (u.n) n) + f_extra:
+ *   (A_S + n (w n)^T/|S|) u + V[beta P_tau u] = U - V[-p n + f_extra]   (slip = 0), or
+ *   (A_S + n (w n)^T/|S|) u = U - V[f(p, u_prev)]                       (slip = 1, u_prev = entry u).
+ * U: host double[3] far-field velocity; p: device [n]; f_extra: device
+ * [3][n] or NULL; u: device [3][n], initial guess on entry. */
+int stokes_solve(sdbie_plan plan, const sdbie_params* prm, const double U[3], const double* p,
+                 const double* f_extra, double* u, const sdbie_opts* opts, sdbie_info* info,
+                 void* stream);
+
+/* Coupled problem by the Dirichlet-Neumann iteration (sections "The
+ * Dirichlet-Neumann iterative method" and "Algorithm"): Darcy solve with
+ * the normal velocity, Stokes solve with the traction from p_D, relaxed
+ * update of the interface unknown (outer = 0) or GMRES on the affine
+ * interface map (outer = 1).  Outputs p (device [n]), u (device [3][n])
+ * and the drag (host double[3]) by eq. (drag_int), D = sum_j w_j f_j.
+ * f_extra (device [3][n] or NULL) is a prescribed extra traction (the
+ * paper's benchmark adds the exact viscous traction of its test problem). */
+int ddm_solve(sdbie_plan plan, const sdbie_params* prm, const double U[3], const double* f_extra,
+              double* p, double* u, double drag[3], const sdbie_opts* opts, sdbie_info* info,
+              void* stream);
+
+/* Message describing the last error returned on the calling thread. */
+const char* sdbie_last_error(void);
+
+/* Library ABI version (incremented on incompatible changes). */
+int sdbie_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDBIE_H */

@@ -1,0 +1,9 @@
+"""sdbie: regularised boundary-integral Stokes-Darcy solver on one MI355X (gfx950).
+
+The compute path is the HIP library libsdbie.so (C ABI in include/sdbie.h);
+this package is its ctypes binding.  See `binding` for the call surface.
+"""
+from .binding import (  # noqa: F401
+    DL_RAW, DL_SUB, FP64, MIXED, SL, Plan, SdbieError, darcy_solve, ddm_solve, default_opts,
+    laplace_layer_apply, lib, stokes_layer_apply, stokes_solve, workspace_bytes,
+)

@@ -1,0 +1,226 @@
+// Vector kernels of the Krylov solver and the interface loop (double).
+//
+// Reductions are deterministic: a fixed grid of kRedBlocks blocks writes one
+// partial per block (wave shuffles, then LDS in a fixed order) and a single
+// block adds the partials in a fixed order.  Results are bitwise
+// reproducible from run to run.
+#include "internal.h"
+
+namespace sdbie {
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// block of 256 lanes -> sum in lane 0 (fixed order)
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_dot_partial(const double* __restrict__ a, const double* __restrict__ b,
+                                                     int64_t len, double* __restrict__ part) {
+    __shared__ double sh[4];
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < len; i += (int64_t)gridDim.x * 256)
+        s += b ? a[i] * b[i] : a[i];
+    const double r = block_sum(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+// part: [nb][k] -> out[j] = sum_b part[b][j], one block per j
+__global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ part, int nb, int k,
+                                                     double* __restrict__ out) {
+    __shared__ double sh[4];
+    const int j = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) s += part[(int64_t)b * k + j];
+    const double r = block_sum(s, sh);
+    if (threadIdx.x == 0) out[j] = r;
+}
+
+// part[b][j] = sum over block b's chunk of V_j . w
+__global__ __launch_bounds__(256) void k_multidot_partial(const double* __restrict__ V, int64_t ld, int k,
+                                                          const double* __restrict__ w, int64_t len,
+                                                          double* __restrict__ part) {
+    __shared__ double sh[4];
+    const int64_t chunk = (len + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk;
+    const int64_t hi = lo + chunk < len ? lo + chunk : len;
+    for (int j = 0; j < k; ++j) {
+        const double* v = V + (int64_t)j * ld;
+        double s = 0.0;
+        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) s += v[i] * w[i];
+        const double r = block_sum(s, sh);
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * k + j] = r;
+    }
+}
+
+__global__ void k_multi_axpy(const double* __restrict__ V, int64_t ld, int k, const double* __restrict__ h,
+                             double sign, double* __restrict__ w, int64_t len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) s += h[j] * V[(int64_t)j * ld + i];
+    w[i] += sign * s;
+}
+
+__global__ void k_axpby(double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                        double* __restrict__ out, int64_t len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+__global__ void k_fill(double v, double* __restrict__ out, int64_t len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) out[i] = v;
+}
+
+__global__ void k_add_scalar(double* __restrict__ x, const double* __restrict__ d, double scale, int64_t len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) x[i] += scale * d[0];
+}
+
+__global__ void k_normal_comp(int64_t n, const double* __restrict__ nrm, const double* __restrict__ u,
+                              double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = nrm[i] * u[i] + nrm[n + i] * u[n + i] + nrm[2 * n + i] * u[2 * n + i];
+}
+
+__global__ void k_traction(int64_t n, const double* __restrict__ nrm, const double* __restrict__ p,
+                           const double* __restrict__ u, double beta, const double* __restrict__ fx,
+                           double* __restrict__ f) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double nx = nrm[i], ny = nrm[n + i], nz = nrm[2 * n + i];
+    const double pi = p ? p[i] : 0.0;
+    double tx = 0.0, ty = 0.0, tz = 0.0;
+    if (u && beta != 0.0) {
+        const double ux = u[i], uy = u[n + i], uz = u[2 * n + i];
+        const double un = ux * nx + uy * ny + uz * nz;
+        tx = beta * (ux - un * nx);
+        ty = beta * (uy - un * ny);
+        tz = beta * (uz - un * nz);
+    }
+    f[i] = -pi * nx + tx + (fx ? fx[i] : 0.0);
+    f[n + i] = -pi * ny + ty + (fx ? fx[n + i] : 0.0);
+    f[2 * n + i] = -pi * nz + tz + (fx ? fx[2 * n + i] : 0.0);
+}
+
+__global__ void k_gather(int64_t n, int comps, const int32_t* __restrict__ perm, const double* __restrict__ src,
+                         double* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = perm[i];
+    for (int c = 0; c < comps; ++c) dst[c * n + i] = src[c * n + o];
+}
+
+__global__ void k_scatter(int64_t n, int comps, const int32_t* __restrict__ perm, const double* __restrict__ src,
+                          double* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t o = perm[i];
+    for (int c = 0; c < comps; ++c) dst[c * n + o] = src[c * n + i];
+}
+
+__global__ void k_check_finite(const double* __restrict__ a, int64_t len, int* __restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len && !isfinite(a[i])) flag[0] = 1;
+}
+
+inline unsigned nblk(int64_t len) { return (unsigned)((len + 255) / 256); }
+
+}  // namespace
+
+void dev_dot(const Plan& P, const double* a, const double* b, int64_t len, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_partial, dim3(kRedBlocks), dim3(256), 0, s, a, b, len, P.red);
+    SDBIE_LAUNCHED();
+    hipLaunchKernelGGL(k_reduce_cols, dim3(1), dim3(256), 0, s, (const double*)P.red, kRedBlocks, 1, out);
+    SDBIE_LAUNCHED();
+}
+
+void dev_multidot(const Plan& P, const double* V, int64_t ld, int k, const double* w, int64_t len,
+                  double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_multidot_partial, dim3(kRedBlocks), dim3(256), 0, s, V, ld, k, w, len, P.red);
+    SDBIE_LAUNCHED();
+    hipLaunchKernelGGL(k_reduce_cols, dim3(k), dim3(256), 0, s, (const double*)P.red, kRedBlocks, k, out);
+    SDBIE_LAUNCHED();
+}
+
+void dev_multi_axpy_sub(const double* V, int64_t ld, int k, const double* h, double* w, int64_t len,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_multi_axpy, dim3(nblk(len)), dim3(256), 0, s, V, ld, k, h, -1.0, w, len);
+    SDBIE_LAUNCHED();
+}
+
+void dev_multi_axpy_add(const double* V, int64_t ld, int k, const double* y, double* x, int64_t len,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_multi_axpy, dim3(nblk(len)), dim3(256), 0, s, V, ld, k, y, 1.0, x, len);
+    SDBIE_LAUNCHED();
+}
+
+void dev_axpby(double a, const double* x, double b, const double* y, double* out, int64_t len, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby, dim3(nblk(len)), dim3(256), 0, s, a, x, b, y, out, len);
+    SDBIE_LAUNCHED();
+}
+
+void dev_scale(double a, const double* x, double* out, int64_t len, hipStream_t s) {
+    dev_axpby(a, x, 0.0, nullptr, out, len, s);
+}
+
+void dev_fill(double v, double* out, int64_t len, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill, dim3(nblk(len)), dim3(256), 0, s, v, out, len);
+    SDBIE_LAUNCHED();
+}
+
+void dev_add_scaled_scalar(double* x, const double* d, double scale, int64_t len, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_scalar, dim3(nblk(len)), dim3(256), 0, s, x, d, scale, len);
+    SDBIE_LAUNCHED();
+}
+
+void dev_normal_component(const Plan& P, const double* u, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_normal_comp, dim3(nblk(P.n)), dim3(256), 0, s, P.n, (const double*)P.nrm, u, out);
+    SDBIE_LAUNCHED();
+}
+
+void dev_traction(const Plan& P, const double* p, const double* u, double beta, const double* f_extra,
+                  double* f, hipStream_t s) {
+    hipLaunchKernelGGL(k_traction, dim3(nblk(P.n)), dim3(256), 0, s, P.n, (const double*)P.nrm, p, u, beta,
+                       f_extra, f);
+    SDBIE_LAUNCHED();
+}
+
+void dev_gather(const Plan& P, const double* src, double* dst, int comps, hipStream_t s) {
+    hipLaunchKernelGGL(k_gather, dim3(nblk(P.n)), dim3(256), 0, s, P.n, comps, (const int32_t*)P.perm, src, dst);
+    SDBIE_LAUNCHED();
+}
+
+void dev_scatter(const Plan& P, const double* src, double* dst, int comps, hipStream_t s) {
+    hipLaunchKernelGGL(k_scatter, dim3(nblk(P.n)), dim3(256), 0, s, P.n, comps, (const int32_t*)P.perm, src, dst);
+    SDBIE_LAUNCHED();
+}
+
+void dev_check_finite(const double* a, int64_t len, int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_finite, dim3(nblk(len)), dim3(256), 0, s, a, len, flag);
+    SDBIE_LAUNCHED();
+}
+
+double host_read_scalar(const double* d, hipStream_t s) {
+    double v = 0.0;
+    SDBIE_HIP(hipMemcpyAsync(&v, d, sizeof(double), hipMemcpyDeviceToHost, s));
+    SDBIE_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+}  // namespace sdbie

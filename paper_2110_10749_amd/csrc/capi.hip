@@ -1,0 +1,335 @@
+// C ABI of the library: argument checks, workspace layout, plans, and the
+// conversion between the caller's node order and the staged (Morton) order.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "solver.h"
+
+namespace sdbie {
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr double kPi = 3.14159265358979323846;
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int64_t next_pow2(int64_t n) {
+    int64_t p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
+struct Layout {
+    size_t x, nrm, w, wn, x32, n32, w32, perm, keys, partial, red, scal, vecs, basis_in, basis_out, total;
+};
+
+Layout layout(int64_t n, int m) {
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t d = sizeof(double), f = sizeof(float);
+    L.x = take(3 * n * d);
+    L.nrm = take(3 * n * d);
+    L.w = take(n * d);
+    L.wn = take(3 * n * d);
+    L.x32 = take(3 * n * f);
+    L.n32 = take(3 * n * f);
+    L.w32 = take(n * f);
+    L.perm = take(n * sizeof(int32_t));
+    L.keys = take(next_pow2(n) * sizeof(uint64_t));
+    L.partial = take((size_t)choose_splits(n) * 3 * n * d);
+    L.red = take((size_t)kRedBlocks * (m + 2) * d);
+    L.scal = take((size_t)(kScalGmres + 6 * (m + 2) + 64 > 1024 ? kScalGmres + 6 * (m + 2) + 64 : 1024) * d);
+    L.vecs = take((size_t)kNumVec * 3 * n * d);
+    L.basis_in = take((size_t)(m + 1) * 3 * n * d);
+    L.basis_out = take((size_t)(m + 1) * n * d);
+    L.total = off;
+    return L;
+}
+
+void fail(int code, const std::string& msg) { throw Error(code, msg); }
+
+void check_finite_pos(double v, const char* name) {
+    if (!(std::isfinite(v) && v > 0.0)) fail(SDBIE_ERR_ARG, std::string(name) + " must be finite and > 0");
+}
+
+Plan& plan_of(sdbie_plan p) {
+    if (!p) fail(SDBIE_ERR_ARG, "null plan");
+    return *reinterpret_cast<Plan*>(p);
+}
+
+void check_params(const sdbie_params* prm) {
+    if (!prm) fail(SDBIE_ERR_ARG, "null params");
+    check_finite_pos(prm->mu, "mu");
+    check_finite_pos(prm->K, "K");
+    if (!(std::isfinite(prm->alpha) && prm->alpha >= 0.0)) fail(SDBIE_ERR_ARG, "alpha must be finite and >= 0");
+}
+
+sdbie_opts checked_opts(const sdbie_opts* op, const Plan& P) {
+    sdbie_opts o;
+    sdbie_default_opts(&o);
+    if (op) o = *op;
+    check_finite_pos(o.tol_gmres, "tol_gmres");
+    check_finite_pos(o.tol_ddm, "tol_ddm");
+    if (!(o.theta > 0.0 && o.theta < 1.0)) fail(SDBIE_ERR_ARG, "theta must lie in (0, 1)");
+    if (o.restart < 1 || o.restart > P.max_restart)
+        fail(SDBIE_ERR_ARG, "restart must lie in [1, max_restart of the plan]");
+    if (o.maxit_gmres < 1 || o.maxit_ddm < 1) fail(SDBIE_ERR_ARG, "iteration limits must be >= 1");
+    if (o.outer != 0 && o.outer != 1) fail(SDBIE_ERR_ARG, "outer must be 0 or 1");
+    if (o.slip != 0 && o.slip != 1) fail(SDBIE_ERR_ARG, "slip must be 0 or 1");
+    if (o.prec != SDBIE_FP64 && o.prec != SDBIE_MIXED) fail(SDBIE_ERR_ARG, "prec must be SDBIE_FP64 or SDBIE_MIXED");
+    if (!(o.tol_mixed > 0.0 && o.tol_mixed < 1.0)) fail(SDBIE_ERR_ARG, "tol_mixed must lie in (0, 1)");
+    if (o.refine_max < 1) fail(SDBIE_ERR_ARG, "refine_max must be >= 1");
+    return o;
+}
+
+template <class F>
+int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const Error& e) {
+        g_last_error = e.what();
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_last_error = "host allocation failed";
+        return SDBIE_ERR_DEVICE;
+    } catch (const std::exception& e) {
+        g_last_error = e.what();
+        return SDBIE_ERR_DEVICE;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return SDBIE_ERR_DEVICE;
+    }
+}
+
+hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool is_zero(Ctx& c, const double* a, int64_t len) { return c.norm(a, len) == 0.0; }
+
+}  // namespace
+
+size_t workspace_bytes(int64_t n, int max_restart) { return layout(n, max_restart).total; }
+
+void carve_workspace(Plan& P, void* ws) {
+    const Layout L = layout(P.n, P.max_restart);
+    char* b = static_cast<char*>(ws);
+    P.x = reinterpret_cast<double*>(b + L.x);
+    P.nrm = reinterpret_cast<double*>(b + L.nrm);
+    P.w = reinterpret_cast<double*>(b + L.w);
+    P.wn = reinterpret_cast<double*>(b + L.wn);
+    P.x32 = reinterpret_cast<float*>(b + L.x32);
+    P.n32 = reinterpret_cast<float*>(b + L.n32);
+    P.w32 = reinterpret_cast<float*>(b + L.w32);
+    P.perm = reinterpret_cast<int32_t*>(b + L.perm);
+    P.keys = reinterpret_cast<uint64_t*>(b + L.keys);
+    P.npow2 = next_pow2(P.n);
+    P.partial = reinterpret_cast<double*>(b + L.partial);
+    P.red = reinterpret_cast<double*>(b + L.red);
+    P.scal = reinterpret_cast<double*>(b + L.scal);
+    P.vecs = reinterpret_cast<double*>(b + L.vecs);
+    P.basis_in = reinterpret_cast<double*>(b + L.basis_in);
+    P.basis_out = reinterpret_cast<double*>(b + L.basis_out);
+}
+
+}  // namespace sdbie
+
+using namespace sdbie;
+
+extern "C" {
+
+void sdbie_default_opts(sdbie_opts* o) {
+    if (!o) return;
+    o->tol_gmres = 1e-10;
+    o->tol_ddm = 1e-8;
+    o->theta = 0.5;
+    o->maxit_gmres = 500;
+    o->restart = 50;
+    o->maxit_ddm = 200;
+    o->outer = 1;
+    o->slip = 0;
+    o->prec = SDBIE_FP64;
+    o->tol_mixed = 1e-5;
+    o->refine_max = 8;
+}
+
+size_t sdbie_workspace_bytes(int64_t n, int max_restart) {
+    if (n < 1 || n > (int64_t)INT32_MAX || max_restart < 1 || max_restart > 200) return 0;
+    return workspace_bytes(n, max_restart);
+}
+
+int sdbie_abi_version(void) { return 1; }
+
+const char* sdbie_last_error(void) { return g_last_error.c_str(); }
+
+int sdbie_plan_create(sdbie_plan* out, const sdbie_surface* s, int max_restart, void* ws, size_t ws_bytes,
+                      void* stream) {
+    return guarded([&]() -> int {
+        if (!out) fail(SDBIE_ERR_ARG, "null plan pointer");
+        *out = nullptr;
+        if (!s || !s->x || !s->nrm || !s->w) fail(SDBIE_ERR_ARG, "null surface array");
+        if (s->n < 1 || s->n > (int64_t)INT32_MAX) fail(SDBIE_ERR_ARG, "n must lie in [1, 2^31)");
+        check_finite_pos(s->delta, "delta");
+        if (max_restart < 1 || max_restart > 200) fail(SDBIE_ERR_ARG, "max_restart must lie in [1, 200]");
+        if (!ws) fail(SDBIE_ERR_WORKSPACE, "null workspace");
+        if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) fail(SDBIE_ERR_WORKSPACE, "workspace not 256-byte aligned");
+        const size_t need = workspace_bytes(s->n, max_restart);
+        if (ws_bytes < need)
+            fail(SDBIE_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+        Plan* P = new Plan();
+        P->n = s->n;
+        P->max_restart = max_restart;
+        P->delta = s->delta;
+        carve_workspace(*P, ws);
+        try {
+            stage_surface(*P, s, stream_of(stream));
+        } catch (...) {
+            delete P;
+            throw;
+        }
+        *out = reinterpret_cast<sdbie_plan>(P);
+        return SDBIE_OK;
+    });
+}
+
+int sdbie_plan_destroy(sdbie_plan plan) {
+    delete reinterpret_cast<Plan*>(plan);
+    return SDBIE_OK;
+}
+
+int64_t sdbie_plan_n(sdbie_plan plan) { return plan ? reinterpret_cast<Plan*>(plan)->n : -1; }
+
+int laplace_layer_apply(sdbie_plan plan, sdbie_layer layer, const double* dens, double* out, sdbie_precision prec,
+                        void* stream) {
+    return guarded([&]() -> int {
+        Plan& P = plan_of(plan);
+        if (!dens || !out) fail(SDBIE_ERR_ARG, "null density or output");
+        if (dens == out) fail(SDBIE_ERR_ARG, "output aliases the density");
+        if (prec != SDBIE_FP64 && prec != SDBIE_MIXED) fail(SDBIE_ERR_ARG, "bad precision");
+        hipStream_t st = stream_of(stream);
+        double* in = P.vec(kVecIn);
+        dev_gather(P, dens, in, 1, st);
+        PassDesc d;
+        d.mixed = prec == SDBIE_MIXED;
+        d.out = out;
+        d.scatter = true;
+        switch (layer) {
+            case SDBIE_SL: d.sl = true; d.c_sl = -1.0 / (4.0 * kPi); d.sl_dens = in; break;
+            case SDBIE_DL_RAW: d.dl = true; d.c_dl = -1.0 / (4.0 * kPi); d.dl_dens = in; break;
+            case SDBIE_DL_SUB: d.dl = true; d.sub = true; d.c_dl = 1.0 / (4.0 * kPi); d.dl_dens = in; break;
+            default: fail(SDBIE_ERR_ARG, "bad layer");
+        }
+        launch_laplace_pass(P, d, st);
+        return SDBIE_OK;
+    });
+}
+
+int stokes_layer_apply(sdbie_plan plan, double mu, sdbie_layer layer, const double* dens, double* out,
+                       sdbie_precision prec, void* stream) {
+    return guarded([&]() -> int {
+        Plan& P = plan_of(plan);
+        if (!dens || !out) fail(SDBIE_ERR_ARG, "null density or output");
+        if (dens == out) fail(SDBIE_ERR_ARG, "output aliases the density");
+        if (prec != SDBIE_FP64 && prec != SDBIE_MIXED) fail(SDBIE_ERR_ARG, "bad precision");
+        hipStream_t st = stream_of(stream);
+        double* in = P.vec(kVecIn);
+        dev_gather(P, dens, in, 3, st);
+        PassDesc d;
+        d.mixed = prec == SDBIE_MIXED;
+        d.out = out;
+        d.scatter = true;
+        switch (layer) {
+            case SDBIE_SL:
+                check_finite_pos(mu, "mu");
+                d.sl = true; d.c_sl = 1.0 / (8.0 * kPi * mu); d.sl_dens = in;
+                break;
+            case SDBIE_DL_RAW: d.dl = true; d.c_dl = -3.0 / (4.0 * kPi); d.dl_dens = in; break;
+            case SDBIE_DL_SUB:
+                d.dl = true; d.sub = true; d.c_dl = -3.0 / (4.0 * kPi); d.dl_dens = in; d.base = in;
+                break;
+            default: fail(SDBIE_ERR_ARG, "bad layer");
+        }
+        launch_stokes_pass(P, d, st);
+        return SDBIE_OK;
+    });
+}
+
+int darcy_solve(sdbie_plan plan, const sdbie_params* prm, const double* vn, double* p, const sdbie_opts* opts,
+                sdbie_info* info, void* stream) {
+    return guarded([&]() -> int {
+        Plan& P = plan_of(plan);
+        check_params(prm);
+        if (!vn || !p) fail(SDBIE_ERR_ARG, "null vn or p");
+        const sdbie_opts o = checked_opts(opts, P);
+        Ctx c(P, stream_of(stream), o);
+        double* v = P.vec(kVecIn);
+        double* ps = P.vec(kVecP);
+        dev_gather(P, vn, v, 1, c.s);
+        dev_gather(P, p, ps, 1, c.s);
+        c.darcy(*prm, v, ps, !is_zero(c, ps, P.n), nullptr);
+        dev_scatter(P, ps, p, 1, c.s);
+        SDBIE_HIP(hipStreamSynchronize(c.s));
+        c.finish();
+        if (info) *info = c.info;
+        return c.converged ? SDBIE_OK : SDBIE_NOT_CONVERGED;
+    });
+}
+
+int stokes_solve(sdbie_plan plan, const sdbie_params* prm, const double U[3], const double* p, const double* f_extra,
+                 double* u, const sdbie_opts* opts, sdbie_info* info, void* stream) {
+    return guarded([&]() -> int {
+        Plan& P = plan_of(plan);
+        check_params(prm);
+        if (!U || !p || !u) fail(SDBIE_ERR_ARG, "null U, p or u");
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(U[k])) fail(SDBIE_ERR_ARG, "non-finite U");
+        const sdbie_opts o = checked_opts(opts, P);
+        Ctx c(P, stream_of(stream), o);
+        double* ps = P.vec(kVecP);
+        double* us = P.vec(kVecU);
+        double* fx = f_extra ? P.vec(kVecFx) : nullptr;
+        dev_gather(P, p, ps, 1, c.s);
+        dev_gather(P, u, us, 3, c.s);
+        if (fx) dev_gather(P, f_extra, fx, 3, c.s);
+        c.stokes(*prm, U, ps, fx, us, !is_zero(c, us, 3 * P.n), nullptr);
+        dev_scatter(P, us, u, 3, c.s);
+        SDBIE_HIP(hipStreamSynchronize(c.s));
+        c.finish();
+        if (info) *info = c.info;
+        return c.converged ? SDBIE_OK : SDBIE_NOT_CONVERGED;
+    });
+}
+
+int ddm_solve(sdbie_plan plan, const sdbie_params* prm, const double U[3], const double* f_extra, double* p,
+              double* u, double drag[3], const sdbie_opts* opts, sdbie_info* info, void* stream) {
+    return guarded([&]() -> int {
+        Plan& P = plan_of(plan);
+        check_params(prm);
+        if (!U || !p || !u || !drag) fail(SDBIE_ERR_ARG, "null U, p, u or drag");
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(U[k])) fail(SDBIE_ERR_ARG, "non-finite U");
+        const sdbie_opts o = checked_opts(opts, P);
+        if (o.outer == 1 && o.slip == 1 && prm->alpha != 0.0)
+            fail(SDBIE_ERR_ARG, "outer GMRES needs the implicit slip form (slip = 0)");
+        Ctx c(P, stream_of(stream), o);
+        double* ps = P.vec(kVecP);
+        double* us = P.vec(kVecU);
+        double* fx = f_extra ? P.vec(kVecFx) : nullptr;
+        if (fx) dev_gather(P, f_extra, fx, 3, c.s);
+        c.ddm(*prm, U, fx, ps, us, drag);
+        dev_scatter(P, ps, p, 1, c.s);
+        dev_scatter(P, us, u, 3, c.s);
+        SDBIE_HIP(hipStreamSynchronize(c.s));
+        c.finish();
+        if (info) *info = c.info;
+        return c.converged ? SDBIE_OK : SDBIE_NOT_CONVERGED;
+    });
+}
+
+}  // extern "C"

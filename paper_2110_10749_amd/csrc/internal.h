@@ -1,0 +1,133 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/sdbie.h"
+
+namespace sdbie {
+
+// Error carried inside the library; converted to a status code at the C ABI.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define SDBIE_HIP(call)                                                                     \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            throw ::sdbie::Error(SDBIE_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define SDBIE_LAUNCHED() SDBIE_HIP(hipGetLastError())
+
+constexpr int kTPB = 256;        // threads per block of the pair kernels (4 waves)
+constexpr int kTile = 256;       // sources staged in LDS per tile
+constexpr int kMaxSplit = 64;    // source splits of one pair pass
+constexpr int kRedBlocks = 512;  // blocks of the deterministic reductions
+
+// Pair-sum passes --------------------------------------------------------------
+// Laplace pass:  out_i = base_i + c_dl * sum_j w_j (q_j - sub*q_i)(D.n_j) k2
+//                               + c_sl * sum_j w_j g_j k1 + comp * cw_i
+// Stokes pass:   out_i = base_i + c_dl * sum_j w_j ((u_j - sub*u_i).D)(D.n_j) D k4
+//                               + c_sl * sum_j w_j [f_j k1 + D (D.f_j) k3]
+//                               + comp * n_i
+// where the Stokes single-layer density is f = sl_dens, or beta * P_tau u
+// when slip_beta != 0 (computed on the fly from the double-layer density).
+struct PassDesc {
+    bool dl = false, sl = false, sub = false;
+    double c_dl = 0.0, c_sl = 0.0;
+    const double* dl_dens = nullptr;  // sorted
+    const double* sl_dens = nullptr;  // sorted
+    double slip_beta = 0.0;           // Stokes only
+    const double* base = nullptr;     // sorted, [n] or [3][n], added to the result (nullable)
+    double base_scale = 1.0;
+    const double* comp = nullptr;     // device scalar (nullable): completion coefficient
+    double comp_scale = 0.0;
+    const double* add_const = nullptr; // host double[3] added to every node (nullable)
+    double* out = nullptr;            // sorted, or original order when scatter
+    bool scatter = false;             // write out[perm[i]] instead of out[i]
+    bool mixed = false;
+};
+
+struct Plan {
+    int64_t n = 0;
+    int max_restart = 0;
+    double delta = 0.0;
+    double area = 0.0;  // sum of weights
+    // sorted node data (double)
+    double* x = nullptr;    // [3][n]
+    double* nrm = nullptr;  // [3][n]
+    double* w = nullptr;    // [n]
+    double* wn = nullptr;   // [3][n] w_j n_j
+    // sorted node data (float)
+    float* x32 = nullptr;   // [3][n]
+    float* n32 = nullptr;   // [3][n]
+    float* w32 = nullptr;   // [n]
+    int32_t* perm = nullptr;  // sorted index -> caller index
+    uint64_t* keys = nullptr; // sort scratch, [npow2]
+    int64_t npow2 = 0;
+    // scratch
+    double* partial = nullptr;  // [kMaxSplit][3][n]
+    double* red = nullptr;      // reduction partials [kRedBlocks * 64]
+    double* scal = nullptr;     // small device scalars / columns [256]
+    double* vecs = nullptr;     // general work vectors, kNumVec x [3][n]
+    double* basis_in = nullptr;   // inner GMRES basis [(max_restart+1)][3n]
+    double* basis_out = nullptr;  // outer GMRES basis [(max_restart+1)][n]
+    double* host_pinned = nullptr;  // not used (host buffers are plain)
+    // bookkeeping for info
+    int64_t applies_fp64 = 0, applies_mixed = 0;
+    double pairs = 0.0;
+    double* vec(int k) const { return vecs + (size_t)k * 3 * n; }
+};
+
+constexpr int kNumVec = 24;
+
+size_t workspace_bytes(int64_t n, int max_restart);
+void carve_workspace(Plan& P, void* ws);
+
+// kernels (pair_kernels.hip) ----------------------------------------------------
+void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t s);
+void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t s);
+int choose_splits(int64_t n);
+
+// staging (stage.hip) --------------------------------------------------------------
+void stage_surface(Plan& P, const sdbie_surface* s, hipStream_t st);
+
+// vector kernels (blas.hip) ----------------------------------------------------------
+// deterministic dot product sum_i a_i b_i (len elements) -> device scalar *out
+void dev_dot(const Plan& P, const double* a, const double* b, int64_t len, double* out, hipStream_t s);
+// dots of w against k columns of V (column stride ld) -> out[0..k-1]
+void dev_multidot(const Plan& P, const double* V, int64_t ld, int k, const double* w, int64_t len,
+                  double* out, hipStream_t s);
+// w -= sum_j h[j] V_j  (h on device)
+void dev_multi_axpy_sub(const double* V, int64_t ld, int k, const double* h, double* w, int64_t len,
+                        hipStream_t s);
+// x += sum_j y[j] V_j  (y on device)
+void dev_multi_axpy_add(const double* V, int64_t ld, int k, const double* y, double* x, int64_t len,
+                        hipStream_t s);
+void dev_axpby(double a, const double* x, double b, const double* y, double* out, int64_t len, hipStream_t s);
+void dev_scale(double a, const double* x, double* out, int64_t len, hipStream_t s);
+void dev_fill(double v, double* out, int64_t len, hipStream_t s);
+void dev_add_scaled_scalar(double* x, const double* dscal, double scale, int64_t len, hipStream_t s);
+// out = u.n (per node)
+void dev_normal_component(const Plan& P, const double* u, double* out, hipStream_t s);
+// f = -p n + beta (u - (u.n) n) + f_extra   (u, f_extra nullable)
+void dev_traction(const Plan& P, const double* p, const double* u, double beta, const double* f_extra,
+                  double* f, hipStream_t s);
+// sorted <-> caller order
+void dev_gather(const Plan& P, const double* src, double* dst, int comps, hipStream_t s);
+void dev_scatter(const Plan& P, const double* src, double* dst, int comps, hipStream_t s);
+// non-finite check: *flag (device int) set to 1 if any element is not finite
+void dev_check_finite(const double* a, int64_t len, int* flag, hipStream_t s);
+
+// host-side helpers
+double host_read_scalar(const double* d, hipStream_t s);
+
+}  // namespace sdbie

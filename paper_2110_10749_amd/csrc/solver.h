@@ -1,0 +1,96 @@
+// Solver context: operators, GMRES, local solves and the interface loop.
+#pragma once
+
+#include <functional>
+
+#include "internal.h"
+
+namespace sdbie {
+
+// work-vector slots of Plan::vec (each 3n doubles)
+enum : int {
+    kVecV = 0,        // interface unknown v = u.n
+    kVecVn,           // next interface iterate
+    kVecT0,           // outer GMRES right-hand side
+    kVecPl,           // pressure inside the outer operator
+    kVecUl,           // velocity inside the outer operator
+    kVecDarcyB,       // Darcy right-hand side
+    kVecStokesB,      // Stokes right-hand side
+    kVecTraction,     // traction f
+    kVecRefR,         // refinement residual
+    kVecRefC,         // refinement correction
+    kVecGmresR,       // inner GMRES residual
+    kVecGmresW,       // inner GMRES new Krylov vector
+    kVecOuterR,       // outer GMRES residual
+    kVecOuterW,       // outer GMRES new vector
+    kVecP,            // sorted pressure (entry points)
+    kVecU,            // sorted velocity (entry points)
+    kVecFx,           // sorted extra traction
+    kVecIn,           // sorted input density / misc
+    kVecOut,          // sorted output / misc
+    kVecCoupledP,     // mixed coupled refinement: pressure iterate
+    kVecCoupledU,     // mixed coupled refinement: velocity iterate
+    kVecCoupledR1,    // mixed coupled refinement: Darcy residual
+    kVecCoupledR2,    // mixed coupled refinement: Stokes residual
+    kVecSpare,
+};
+static_assert(kVecSpare < kNumVec, "work-vector slots exceed the workspace");
+
+// device scalar slots of Plan::scal
+enum : int {
+    kScalCompD = 0,
+    kScalCompS = 1,
+    kScalMean = 2,
+    kScalNorm = 3,
+    kScalDrag = 4,   // 3 slots
+    kScalStage = 16, // staging: finite flag (16), bounding box (18..23), weight sum (24)
+    kScalGmres = 32, // inner and outer Hessenberg columns / coefficients
+};
+
+struct GmresWS {
+    double* V = nullptr;
+    double* r = nullptr;
+    double* w = nullptr;
+    double* dcol = nullptr;
+    double* dy = nullptr;
+};
+
+struct GmresOut {
+    int iters = 0;
+    double relres = 0.0;
+    bool conv = false;
+};
+
+struct Ctx {
+    Plan& P;
+    hipStream_t s;
+    const sdbie_opts& o;
+    sdbie_info info;
+    bool converged = true;
+    GmresWS inner, outer;
+
+    Ctx(Plan& plan, hipStream_t st, const sdbie_opts& opts);
+    void finish();
+
+    double norm(const double* a, int64_t len);
+    double dot(const double* a, const double* b, int64_t len);
+    void copy(const double* a, double* b, int64_t len);
+
+    void op_darcy(const double* p, double* out, bool mixed);
+    void op_stokes(const double* u, double* out, double mu, double beta, bool mixed);
+    void single_layer_laplace(const double* g, double scale, double* out, bool mixed);
+    void single_layer_stokes(const double* f, double mu, double scale, const double* add, double* out, bool mixed);
+
+    GmresOut gmres(const GmresWS& ws, const std::function<void(const double*, double*)>& op, const double* b,
+                   double* x, int64_t L, bool x_nonzero, double tol, int restart, int maxit);
+    void solve(const std::function<void(const double*, double*, bool)>& op, const double* b, double* x, int64_t L,
+               bool x_nonzero, double* rbuf, double* cbuf);
+
+    void darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonzero, const double* extra_rhs);
+    void stokes(const sdbie_params& prm, const double U[3], const double* p, const double* fx, double* u,
+                bool u_nonzero, const double* extra_rhs);
+    void ddm(const sdbie_params& prm, const double U[3], const double* fx, double* p, double* u, double drag[3]);
+    void compute_drag(const sdbie_params& prm, const double* p, const double* u, const double* fx, double drag[3]);
+};
+
+}  // namespace sdbie

@@ -1,0 +1,143 @@
+// Surface staging: spatial (Morton) order and the sorted node copies.
+//
+// The pair kernels give each wave 64 consecutive targets; sorting the nodes
+// along a Morton (Z-order) curve makes those 64 targets spatial neighbours,
+// so the near-field branch (rho < rho_cut) is taken by few waves per source
+// and the rest run the plain far-field kernel.
+//
+// Steps (all on the device): bounding box (min/max reduction), 30-bit Morton
+// key per node (10 bits per axis), key<<32 | index sorted by a bitonic network
+// over the next power of two (padding keys = UINT64_MAX; keys are unique, so
+// the order is deterministic), then gather of x, n, w into sorted double
+// arrays, float copies of x, and the weighted normals w n.
+#include "solver.h"
+
+namespace sdbie {
+namespace {
+
+__global__ __launch_bounds__(256) void k_bbox(int64_t n, const double* __restrict__ x, double* __restrict__ out) {
+    // one block per axis: out[2c] = min, out[2c+1] = max
+    __shared__ double smin[256], smax[256];
+    const int c = blockIdx.x;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double v = x[c * n + i];
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+    }
+    smin[threadIdx.x] = lo;
+    smax[threadIdx.x] = hi;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+            smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[2 * c] = smin[0];
+        out[2 * c + 1] = smax[0];
+    }
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ void k_morton(int64_t n, int64_t npow2, const double* __restrict__ x, const double* __restrict__ bb,
+                         uint64_t* __restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npow2) return;
+    if (i >= n) {
+        keys[i] = ~0ull;
+        return;
+    }
+    uint32_t code = 0;
+    // a cube of the largest extent, so the curve is isotropic
+    const double ext = fmax(fmax(bb[1] - bb[0], bb[3] - bb[2]), bb[5] - bb[4]);
+    const double sc = ext > 0.0 ? 1023.0 / ext : 0.0;
+    for (int c = 0; c < 3; ++c) {
+        double t = (x[c * n + i] - bb[2 * c]) * sc;
+        t = fmin(fmax(t, 0.0), 1023.0);
+        code |= spread10((uint32_t)t) << (2 - c);
+    }
+    keys[i] = ((uint64_t)code << 32) | (uint64_t)i;
+}
+
+__global__ void k_bitonic(uint64_t* __restrict__ keys, int64_t npow2, int64_t j, int64_t k) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npow2) return;
+    const int64_t l = i ^ j;
+    if (l > i) {
+        const uint64_t a = keys[i], b = keys[l];
+        const bool up = (i & k) == 0;
+        if ((a > b) == up) {
+            keys[i] = b;
+            keys[l] = a;
+        }
+    }
+}
+
+__global__ void k_stage(int64_t n, const uint64_t* __restrict__ keys, const double* __restrict__ x,
+                        const double* __restrict__ nrm, const double* __restrict__ w, int32_t* __restrict__ perm,
+                        double* __restrict__ xs, double* __restrict__ ns, double* __restrict__ wsrt,
+                        double* __restrict__ wn, float* __restrict__ x32, float* __restrict__ n32,
+                        float* __restrict__ w32) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int64_t o = (int64_t)(keys[k] & 0xffffffffull);
+    perm[k] = (int32_t)o;
+    const double wk = w[o];
+    wsrt[k] = wk;
+    w32[k] = (float)wk;
+    for (int c = 0; c < 3; ++c) {
+        const double xv = x[c * n + o], nv = nrm[c * n + o];
+        xs[c * n + k] = xv;
+        ns[c * n + k] = nv;
+        wn[c * n + k] = wk * nv;
+        x32[c * n + k] = (float)xv;
+        n32[c * n + k] = (float)nv;
+    }
+}
+
+}  // namespace
+
+void stage_surface(Plan& P, const sdbie_surface* s, hipStream_t st) {
+    const int64_t n = P.n;
+    // finite check of the node data first (Morton keys of NaN are meaningless)
+    int* flag = reinterpret_cast<int*>(P.scal + kScalStage);
+    SDBIE_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+    dev_check_finite(s->x, 3 * n, flag, st);
+    dev_check_finite(s->nrm, 3 * n, flag, st);
+    dev_check_finite(s->w, n, flag, st);
+    int hflag = 0;
+    SDBIE_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    SDBIE_HIP(hipStreamSynchronize(st));
+    if (hflag) throw Error(SDBIE_ERR_NONFINITE, "non-finite node coordinates, normals or weights");
+
+    double* bb = P.scal + kScalStage + 2;
+    hipLaunchKernelGGL(k_bbox, dim3(3), dim3(256), 0, st, n, s->x, bb);
+    SDBIE_LAUNCHED();
+    const unsigned nb = (unsigned)((P.npow2 + 255) / 256);
+    hipLaunchKernelGGL(k_morton, dim3(nb), dim3(256), 0, st, n, P.npow2, s->x, (const double*)bb, P.keys);
+    SDBIE_LAUNCHED();
+    for (int64_t k = 2; k <= P.npow2; k <<= 1)
+        for (int64_t j = k >> 1; j > 0; j >>= 1) {
+            hipLaunchKernelGGL(k_bitonic, dim3(nb), dim3(256), 0, st, P.keys, P.npow2, j, k);
+            SDBIE_LAUNCHED();
+        }
+    hipLaunchKernelGGL(k_stage, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, (const uint64_t*)P.keys,
+                       s->x, s->nrm, s->w, P.perm, P.x, P.nrm, P.w, P.wn, P.x32, P.n32, P.w32);
+    SDBIE_LAUNCHED();
+    dev_dot(P, P.w, nullptr, n, P.scal + kScalStage + 8, st);
+    P.area = host_read_scalar(P.scal + kScalStage + 8, st);
+    if (!(P.area > 0.0)) throw Error(SDBIE_ERR_ARG, "the quadrature weights sum to zero");
+}
+
+}  // namespace sdbie

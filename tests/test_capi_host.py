@@ -1,0 +1,84 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/sdbie.h declares, and rejects invalid arguments
+before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sdbie.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2110_10749_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2110_10749_amd import build
+        build.build()
+    return binding.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "defined")))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 12, names
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in sdbie.h but not exported"
+
+
+def test_abi_version_and_default_opts(L):
+    from paper_2110_10749_amd import binding
+    assert L.sdbie_abi_version() == 1
+    o = binding.default_opts()
+    assert o.tol_gmres == 1e-10 and o.tol_ddm == 1e-8 and o.theta == 0.5
+    assert o.restart == 50 and o.outer == 1 and o.slip == 0 and o.prec == 0
+
+
+def test_workspace_bytes(L):
+    from paper_2110_10749_amd import binding
+    a = binding.workspace_bytes(4302, 50)
+    b = binding.workspace_bytes(68166, 50)
+    assert 0 < a < b
+    assert binding.workspace_bytes(68166, 10) < b
+    assert binding.workspace_bytes(0, 50) == 0
+    assert binding.workspace_bytes(100, 0) == 0
+    assert binding.workspace_bytes(100, 1000) == 0
+
+
+def test_invalid_arguments_are_rejected_on_the_host(L):
+    from paper_2110_10749_amd import binding as B
+    # null plan pointer / null surface
+    assert L.sdbie_plan_create(None, None, 50, None, 0, None) == B.ERR_ARG
+    h = ctypes.c_void_p()
+    assert L.sdbie_plan_create(ctypes.byref(h), None, 50, None, 0, None) == B.ERR_ARG
+    assert b"null surface" in L.sdbie_last_error()
+    surf = B.Surface(10, 1, 1, 1, 0.1)
+    # bad delta
+    bad = B.Surface(10, 1, 1, 1, -1.0)
+    assert L.sdbie_plan_create(ctypes.byref(h), ctypes.byref(bad), 50, None, 0, None) == B.ERR_ARG
+    # n out of range
+    bad = B.Surface(0, 1, 1, 1, 0.1)
+    assert L.sdbie_plan_create(ctypes.byref(h), ctypes.byref(bad), 50, None, 0, None) == B.ERR_ARG
+    # workspace missing, misaligned, too small
+    assert L.sdbie_plan_create(ctypes.byref(h), ctypes.byref(surf), 50, None, 0, None) == B.ERR_WORKSPACE
+    assert L.sdbie_plan_create(ctypes.byref(h), ctypes.byref(surf), 50, ctypes.c_void_p(4096 + 8), 10**9, None) == B.ERR_WORKSPACE
+    assert L.sdbie_plan_create(ctypes.byref(h), ctypes.byref(surf), 50, ctypes.c_void_p(4096), 16, None) == B.ERR_WORKSPACE
+    assert b"too small" in L.sdbie_last_error()
+    # null plan on every entry point
+    assert L.laplace_layer_apply(None, 0, None, None, 0, None) == B.ERR_ARG
+    assert L.stokes_layer_apply(None, 1.0, 0, None, None, 0, None) == B.ERR_ARG
+    prm = B.Params(1.0, 1.0, 0.0)
+    U = (ctypes.c_double * 3)(0, 0, 1)
+    assert L.darcy_solve(None, ctypes.byref(prm), None, None, None, None, None) == B.ERR_ARG
+    assert L.stokes_solve(None, ctypes.byref(prm), U, None, None, None, None, None, None) == B.ERR_ARG
+    d = (ctypes.c_double * 3)()
+    assert L.ddm_solve(None, ctypes.byref(prm), U, None, None, None, d, None, None, None) == B.ERR_ARG
+    assert L.sdbie_plan_n(None) == -1
