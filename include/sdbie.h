@@ -117,8 +117,9 @@ typedef struct sdbie_plan_s* sdbie_plan;
  * tol_mixed 1e-5, refine_max 8. */
 void sdbie_default_opts(sdbie_opts* o);
 
-/* Bytes of device workspace a plan for n nodes and GMRES restart length up
- * to max_restart needs (0 if the arguments are invalid). */
+/* Bytes of device workspace a plan for n nodes (1 <= n <= 2^23) and GMRES
+ * restart length up to max_restart (1..200) needs (0 if the arguments are
+ * invalid).  Roughly 8 (30 + 3 max_restart) n bytes plus (n/256)^2 * 2. */
 size_t sdbie_workspace_bytes(int64_t n, int max_restart);
 
 /* Stage a surface: spatial (Morton) ordering, double and float copies of the
@@ -169,6 +170,26 @@ int stokes_solve(sdbie_plan plan, const sdbie_params* prm, const double U[3], co
 int ddm_solve(sdbie_plan plan, const sdbie_params* prm, const double U[3], const double* f_extra,
               double* p, double* u, double drag[3], const sdbie_opts* opts, sdbie_info* info,
               void* stream);
+
+/* Kernel timing (diagnostics).  While enabled, every pair-sum kernel launch
+ * records a HIP event pair around the kernel on the stream it runs on.
+ * sdbie_profile_enable(1) clears old records and starts recording;
+ * sdbie_profile_enable(0) clears and stops.  sdbie_profile_read() waits for
+ * the recorded events and writes up to `max` per-variant summaries (count
+ * receives the number of variants): launches, summed kernel milliseconds,
+ * pair evaluations, and the algorithmic far-field flops per pair of that
+ * variant (FMA = 2, add/mul = 1, rsqrt = 1).  Process-wide; not reentrant
+ * with concurrent recording threads.  Errors: ERR_ARG (null count, or null
+ * out with max > 0), ERR_DEVICE. */
+typedef struct {
+    char name[48];
+    int64_t launches;
+    double ms;
+    double pairs;
+    double flops_per_pair;
+} sdbie_kernel_stat;
+int sdbie_profile_enable(int on);
+int sdbie_profile_read(sdbie_kernel_stat* out, int max, int* count);
 
 /* Message describing the last error returned on the calling thread. */
 const char* sdbie_last_error(void);

@@ -74,8 +74,15 @@ def lib():
         L.oracle_stokes_apply.argtypes = [i64, p, p, p, d, d, i32, p, i64, p, p]
         L.oracle_laplace_matrix.argtypes = [i64, p, p, p, d, i32, p]
         L.oracle_stokes_matrix.argtypes = [i64, p, p, p, d, d, i32, p]
+        L.oracle_num_threads.restype = i32
+        L.oracle_num_threads.argtypes = []
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's pair loops run on."""
+    return int(lib().oracle_num_threads())
 
 
 def _ptr(a):

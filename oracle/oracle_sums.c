@@ -285,3 +285,11 @@ void oracle_stokes_matrix(int64_t n, const double* x, const double* nrm, const d
 }
 
 int oracle_abi_version(void) { return 1; }
+
+/* threads the OpenMP loops above use */
+#ifdef _OPENMP
+#include <omp.h>
+int oracle_num_threads(void) { return omp_get_max_threads(); }
+#else
+int oracle_num_threads(void) { return 1; }
+#endif

@@ -5,5 +5,6 @@ this package is its ctypes binding.  See `binding` for the call surface.
 """
 from .binding import (  # noqa: F401
     DL_RAW, DL_SUB, FP64, MIXED, SL, Plan, SdbieError, darcy_solve, ddm_solve, default_opts,
-    laplace_layer_apply, lib, stokes_layer_apply, stokes_solve, workspace_bytes,
+    laplace_layer_apply, lib, profile_enable, profile_read, stokes_layer_apply, stokes_solve,
+    workspace_bytes,
 )

@@ -47,6 +47,11 @@ class Opts(ctypes.Structure):
                 ("tol_mixed", ctypes.c_double), ("refine_max", ctypes.c_int)]
 
 
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("ms", ctypes.c_double),
+                ("pairs", ctypes.c_double), ("flops_per_pair", ctypes.c_double)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("ddm_iters", ctypes.c_int), ("gmres_iters", ctypes.c_int), ("refine_steps", ctypes.c_int),
                 ("applies_fp64", ctypes.c_int64), ("applies_mixed", ctypes.c_int64), ("pairs", ctypes.c_double),
@@ -94,6 +99,10 @@ def lib():
         L.sdbie_last_error.restype = ctypes.c_char_p
         L.sdbie_abi_version.argtypes = []
         L.sdbie_abi_version.restype = i32
+        L.sdbie_profile_enable.argtypes = [i32]
+        L.sdbie_profile_enable.restype = i32
+        L.sdbie_profile_read.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
+        L.sdbie_profile_read.restype = i32
         _lib = L
     return _lib
 
@@ -120,6 +129,21 @@ def _ptr(t):
 
 def _stream(device) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start (and clear) or stop the per-kernel HIP-event timing of pair-sum launches."""
+    _check(lib().sdbie_profile_enable(1 if on else 0))
+
+
+def profile_read() -> list:
+    """Per-variant kernel timing recorded since profile_enable(True) (waits for the events)."""
+    cnt = ctypes.c_int(0)
+    _check(lib().sdbie_profile_read(None, 0, ctypes.byref(cnt)))
+    arr = (KernelStat * max(cnt.value, 1))()
+    _check(lib().sdbie_profile_read(arr, cnt.value, ctypes.byref(cnt)))
+    return [dict(name=a.name.decode(), launches=a.launches, ms=a.ms, pairs=a.pairs,
+                 flops_per_pair=a.flops_per_pair) for a in arr[:cnt.value]]
 
 
 def default_opts(**kw) -> Opts:

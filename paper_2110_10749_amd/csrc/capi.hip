@@ -23,7 +23,8 @@ int64_t next_pow2(int64_t n) {
 }
 
 struct Layout {
-    size_t x, nrm, w, wn, x32, n32, w32, perm, keys, partial, red, scal, vecs, basis_in, basis_out, total;
+    size_t x, nrm, w, wn, px, pn, pw, px32, boxes, mask64, mask32, perm, keys, partial, red, scal, vecs,
+        basis_in, basis_out, total;
 };
 
 Layout layout(int64_t n, int m) {
@@ -39,12 +40,17 @@ Layout layout(int64_t n, int m) {
     L.nrm = take(3 * n * d);
     L.w = take(n * d);
     L.wn = take(3 * n * d);
-    L.x32 = take(3 * n * f);
-    L.n32 = take(3 * n * f);
-    L.w32 = take(n * f);
+    const int64_t nt = (n + kTile - 1) / kTile, npad = nt * kTile;
+    L.px = take(3 * npad * d);
+    L.pn = take(3 * npad * d);
+    L.pw = take(npad * d);
+    L.px32 = take(3 * npad * f);
+    L.boxes = take(nt * 6 * d);
+    L.mask64 = take(nt * nt);
+    L.mask32 = take(nt * nt);
     L.perm = take(n * sizeof(int32_t));
     L.keys = take(next_pow2(n) * sizeof(uint64_t));
-    L.partial = take((size_t)choose_splits(n) * 3 * n * d);
+    L.partial = take((size_t)2 * choose_splits(n) * 3 * n * d);
     L.red = take((size_t)kRedBlocks * (m + 2) * d);
     L.scal = take((size_t)(kScalGmres + 6 * (m + 2) + 64 > 1024 ? kScalGmres + 6 * (m + 2) + 64 : 1024) * d);
     L.vecs = take((size_t)kNumVec * 3 * n * d);
@@ -124,9 +130,15 @@ void carve_workspace(Plan& P, void* ws) {
     P.nrm = reinterpret_cast<double*>(b + L.nrm);
     P.w = reinterpret_cast<double*>(b + L.w);
     P.wn = reinterpret_cast<double*>(b + L.wn);
-    P.x32 = reinterpret_cast<float*>(b + L.x32);
-    P.n32 = reinterpret_cast<float*>(b + L.n32);
-    P.w32 = reinterpret_cast<float*>(b + L.w32);
+    P.ntiles = (int)((P.n + kTile - 1) / kTile);
+    P.npad = (int64_t)P.ntiles * kTile;
+    P.px = reinterpret_cast<double*>(b + L.px);
+    P.pn = reinterpret_cast<double*>(b + L.pn);
+    P.pw = reinterpret_cast<double*>(b + L.pw);
+    P.px32 = reinterpret_cast<float*>(b + L.px32);
+    P.boxes = reinterpret_cast<double*>(b + L.boxes);
+    P.mask64 = reinterpret_cast<uint8_t*>(b + L.mask64);
+    P.mask32 = reinterpret_cast<uint8_t*>(b + L.mask32);
     P.perm = reinterpret_cast<int32_t*>(b + L.perm);
     P.keys = reinterpret_cast<uint64_t*>(b + L.keys);
     P.npow2 = next_pow2(P.n);
@@ -160,7 +172,7 @@ void sdbie_default_opts(sdbie_opts* o) {
 }
 
 size_t sdbie_workspace_bytes(int64_t n, int max_restart) {
-    if (n < 1 || n > (int64_t)INT32_MAX || max_restart < 1 || max_restart > 200) return 0;
+    if (n < 1 || n > kMaxNodes || max_restart < 1 || max_restart > 200) return 0;
     return workspace_bytes(n, max_restart);
 }
 
@@ -174,7 +186,7 @@ int sdbie_plan_create(sdbie_plan* out, const sdbie_surface* s, int max_restart, 
         if (!out) fail(SDBIE_ERR_ARG, "null plan pointer");
         *out = nullptr;
         if (!s || !s->x || !s->nrm || !s->w) fail(SDBIE_ERR_ARG, "null surface array");
-        if (s->n < 1 || s->n > (int64_t)INT32_MAX) fail(SDBIE_ERR_ARG, "n must lie in [1, 2^31)");
+        if (s->n < 1 || s->n > kMaxNodes) fail(SDBIE_ERR_ARG, "n must lie in [1, 2^23]");
         check_finite_pos(s->delta, "delta");
         if (max_restart < 1 || max_restart > 200) fail(SDBIE_ERR_ARG, "max_restart must lie in [1, 200]");
         if (!ws) fail(SDBIE_ERR_WORKSPACE, "null workspace");

@@ -30,6 +30,8 @@ struct Error : std::runtime_error {
 constexpr int kTPB = 256;        // threads per block of the pair kernels (4 waves)
 constexpr int kTile = 256;       // sources staged in LDS per tile
 constexpr int kMaxSplit = 64;    // source splits of one pair pass
+constexpr int64_t kMaxNodes = (int64_t)1 << 23;  // the tile-pair masks grow as (n/256)^2 bytes
+constexpr int kNearUnit = 64;    // sources per work unit of the near-field kernel
 constexpr int kRedBlocks = 512;  // blocks of the deterministic reductions
 
 // Pair-sum passes --------------------------------------------------------------
@@ -66,15 +68,22 @@ struct Plan {
     double* nrm = nullptr;  // [3][n]
     double* w = nullptr;    // [n]
     double* wn = nullptr;   // [3][n] w_j n_j
-    // sorted node data (float)
-    float* x32 = nullptr;   // [3][n]
-    float* n32 = nullptr;   // [3][n]
-    float* w32 = nullptr;   // [n]
+    // sorted node data padded to whole tiles of kTile nodes (pair-kernel sources;
+    // padding nodes sit far outside the body with zero weight and normal)
+    int64_t npad = 0;       // ntiles * kTile
+    int ntiles = 0;
+    double* px = nullptr;   // [3][npad]
+    double* pn = nullptr;   // [3][npad]
+    double* pw = nullptr;   // [npad]
+    float* px32 = nullptr;  // [3][npad]
+    double* boxes = nullptr;   // [ntiles][6] min/max per axis
+    uint8_t* mask64 = nullptr; // [ntiles][ntiles]: 1 if the tile pair may hold a pair with rho < double cutoff
+    uint8_t* mask32 = nullptr; // [ntiles][ntiles]: same with the float cutoff
     int32_t* perm = nullptr;  // sorted index -> caller index
     uint64_t* keys = nullptr; // sort scratch, [npow2]
     int64_t npow2 = 0;
     // scratch
-    double* partial = nullptr;  // [kMaxSplit][3][n]
+    double* partial = nullptr;  // [2 * nsplit][3][n]: far splits then near splits
     double* red = nullptr;      // reduction partials [kRedBlocks * 64]
     double* scal = nullptr;     // small device scalars / columns [256]
     double* vecs = nullptr;     // general work vectors, kNumVec x [3][n]
@@ -96,6 +105,15 @@ void carve_workspace(Plan& P, void* ws);
 void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t s);
 void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t s);
 int choose_splits(int64_t n);
+
+// kernel timing (profile.hip)
+int prof_variant(int family, bool mixed, int code);
+struct ProfScope {
+    ProfScope(int variant, double pairs, hipStream_t s);
+    ~ProfScope();
+    hipStream_t s_;
+    long idx_ = -1;
+};
 
 // staging (stage.hip) --------------------------------------------------------------
 void stage_surface(Plan& P, const sdbie_surface* s, hipStream_t st);

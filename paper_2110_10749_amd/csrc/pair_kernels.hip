@@ -96,82 +96,89 @@ __device__ __forceinline__ void near_factors(T r2, T inv_r, T id, T id2, T& k1, 
 }
 
 struct KArgs {
-    int64_t n;
-    int nsplit;
-    int64_t chunk;
-    const double* x;    // sorted [3][n]
-    const double* nrm;  // sorted [3][n]
-    const double* w;    // sorted [n]
-    const float* x32;   // sorted [3][n]
-    const double* dl_dens;
-    const double* sl_dens;
+    int64_t n;          // real nodes (targets and sources)
+    int64_t npad;       // ntiles * kTile
+    int ntiles;
+    int nsplit;         // far splits (and near splits)
+    int tiles_per_split;
+    const double* x;    // padded sorted coordinates [3][npad]
+    const double* nrm;  // padded sorted normals [3][npad]
+    const double* w;    // padded sorted weights [npad] (0 on padding)
+    const float* x32;   // padded sorted coordinates, float [3][npad]
+    const uint8_t* mask;  // [ntiles][ntiles] near-field tile pairs
+    const double* dl_dens;  // sorted, stride n
+    const double* sl_dens;  // sorted, stride n
     double c_dl, c_sl, slip_beta;
     double inv_delta;
     double rc2;         // (rho_cut * delta)^2
-    double* partial;    // [nsplit][comps][n]
+    double* partial;    // [2 nsplit][C][n]
 };
 
 template <typename T> __device__ __forceinline__ T load_x(const KArgs& a, int c, int64_t j);
-template <> __device__ __forceinline__ double load_x<double>(const KArgs& a, int c, int64_t j) { return a.x[c * a.n + j]; }
-template <> __device__ __forceinline__ float load_x<float>(const KArgs& a, int c, int64_t j) { return a.x32[c * a.n + j]; }
+template <> __device__ __forceinline__ double load_x<double>(const KArgs& a, int c, int64_t j) { return a.x[c * a.npad + j]; }
+template <> __device__ __forceinline__ float load_x<float>(const KArgs& a, int c, int64_t j) { return a.x32[c * a.npad + j]; }
+
+__device__ __forceinline__ double dens_at(const double* d, int64_t n, int c, int64_t j) {
+    return j < n ? d[c * n + j] : 0.0;
+}
 
 // --------------------------------------------------------------------------
 // Laplace: DL term c_dl * w_j (q_j - SUB q_i) (D.n_j) s2/r^3, SL term c_sl * w_j g_j s1/r
 // --------------------------------------------------------------------------
 template <typename T, bool DL, bool SL, bool SUB>
-__global__ __launch_bounds__(kTPB) void laplace_pairs(KArgs a) {
-    __shared__ T sx[kTile], sy[kTile], sz[kTile];
-    __shared__ T snx[DL ? kTile : 1], sny[DL ? kTile : 1], snz[DL ? kTile : 1], sq[DL ? kTile : 1];
-    __shared__ T sg[SL ? kTile : 1];
-
-    const int split = blockIdx.x % a.nsplit;
-    const int64_t i = (int64_t)(blockIdx.x / a.nsplit) * kTPB + threadIdx.x;
-    const bool active = i < a.n;
-    const int64_t ii = active ? i : a.n - 1;
-    const T xi = load_x<T>(a, 0, ii), yi = load_x<T>(a, 1, ii), zi = load_x<T>(a, 2, ii);
-    const T qi = (DL && SUB) ? T(a.dl_dens[ii]) : T(0);
-    const T id = T(a.inv_delta), id2 = id * id;
-    const T rc2 = T(a.rc2);
-
+struct LaplaceOp {
+    static constexpr int C = 1;
+    static constexpr int TD = DL ? kTile : 1, TS = SL ? kTile : 1;
+    struct Smem {
+        T x[kTile], y[kTile], z[kTile];
+        T nx[TD], ny[TD], nz[TD], q[TD];
+        T g[TS];
+    };
+    T xi, yi, zi, qi;
     double acc = 0.0;
-    const int64_t j0 = (int64_t)split * a.chunk;
-    const int64_t j1 = j0 + a.chunk < a.n ? j0 + a.chunk : a.n;
-    for (int64_t base = j0; base < j1; base += kTile) {
-        const int cnt = (int)((j1 - base) < kTile ? (j1 - base) : kTile);
-        __syncthreads();
-        for (int t = threadIdx.x; t < cnt; t += kTPB) {
-            const int64_t j = base + t;
-            sx[t] = load_x<T>(a, 0, j);
-            sy[t] = load_x<T>(a, 1, j);
-            sz[t] = load_x<T>(a, 2, j);
-            const double wj = a.w[j];
-            if (DL) {
-                const double s = a.c_dl * wj;
-                snx[t] = T(s * a.nrm[j]);
-                sny[t] = T(s * a.nrm[a.n + j]);
-                snz[t] = T(s * a.nrm[2 * a.n + j]);
-                sq[t] = T(a.dl_dens[j]);
-            }
-            if (SL) sg[t] = T(a.c_sl * wj * a.sl_dens[j]);
-        }
-        __syncthreads();
-        T tacc = T(0);
-        for (int jj = 0; jj < cnt; ++jj) {
-            const T dx = xi - sx[jj], dy = yi - sy[jj], dz = zi - sz[jj];
-            const T r2 = dx * dx + dy * dy + dz * dz;
-            const T inv_r = rsq(r2);
-            T k1 = inv_r, k2 = inv_r * inv_r * inv_r, k3, k4;
-            if (r2 < rc2) near_factors<T, SL, DL, false, false>(r2, inv_r, id, id2, k1, k2, k3, k4);
-            if (DL) {
-                const T dn = dx * snx[jj] + dy * sny[jj] + dz * snz[jj];
-                tacc += (sq[jj] - qi) * dn * k2;
-            }
-            if (SL) tacc += sg[jj] * k1;
-        }
-        acc += (double)tacc;
+    T tacc = T(0);
+
+    __device__ __forceinline__ void init(const KArgs& a, int64_t i) {
+        xi = load_x<T>(a, 0, i);
+        yi = load_x<T>(a, 1, i);
+        zi = load_x<T>(a, 2, i);
+        qi = (DL && SUB) ? T(dens_at(a.dl_dens, a.n, 0, i)) : T(0);
     }
-    if (active) a.partial[(int64_t)split * a.n + i] = acc;
-}
+    __device__ __forceinline__ void load(Smem& s, int t, int64_t j, const KArgs& a) const {
+        s.x[t] = load_x<T>(a, 0, j);
+        s.y[t] = load_x<T>(a, 1, j);
+        s.z[t] = load_x<T>(a, 2, j);
+        const double wj = a.w[j];
+        if (DL) {
+            const double c = a.c_dl * wj;
+            s.nx[t] = T(c * a.nrm[j]);
+            s.ny[t] = T(c * a.nrm[a.npad + j]);
+            s.nz[t] = T(c * a.nrm[2 * a.npad + j]);
+            s.q[t] = T(dens_at(a.dl_dens, a.n, 0, j));
+        }
+        if (SL) s.g[t] = T(a.c_sl * wj * dens_at(a.sl_dens, a.n, 0, j));
+    }
+    template <bool NEAR>
+    __device__ __forceinline__ void pair(const Smem& s, int jj, T id, T id2, T rc2) {
+        const T dx = xi - s.x[jj], dy = yi - s.y[jj], dz = zi - s.z[jj];
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const T inv_r = rsq(r2);
+        T k1 = inv_r, k2 = inv_r * inv_r * inv_r, k3, k4;
+        if (NEAR && r2 < rc2) near_factors<T, SL, DL, false, false>(r2, inv_r, id, id2, k1, k2, k3, k4);
+        if (DL) {
+            const T dn = dx * s.nx[jj] + dy * s.ny[jj] + dz * s.nz[jj];
+            tacc += (s.q[jj] - qi) * dn * k2;
+        }
+        if (SL) tacc += s.g[jj] * k1;
+    }
+    __device__ __forceinline__ void flush() {
+        acc += (double)tacc;
+        tacc = T(0);
+    }
+    __device__ __forceinline__ void store(const KArgs& a, int slot, int64_t i) const {
+        a.partial[(int64_t)slot * a.n + i] = acc;
+    }
+};
 
 // --------------------------------------------------------------------------
 // Stokes: DL term c_dl w_j ((u_j - SUB u_i).D)(D.n_j) D s4/r^5,
@@ -179,115 +186,173 @@ __global__ __launch_bounds__(kTPB) void laplace_pairs(KArgs a) {
 //         f_j = sl_dens_j, or beta (u_j - (u_j.n_j) n_j) when SLIP.
 // --------------------------------------------------------------------------
 template <typename T, bool DL, bool SL, bool SUB, bool SLIP>
-__global__ __launch_bounds__(kTPB) void stokes_pairs(KArgs a) {
-    constexpr int TD = DL ? kTile : 1;
-    constexpr int TS = SL ? kTile : 1;
-    __shared__ T sx[kTile], sy[kTile], sz[kTile];
-    __shared__ T snx[TD], sny[TD], snz[TD], sux[TD], suy[TD], suz[TD];
-    __shared__ T sfx[TS], sfy[TS], sfz[TS];
-
-    const int split = blockIdx.x % a.nsplit;
-    const int64_t i = (int64_t)(blockIdx.x / a.nsplit) * kTPB + threadIdx.x;
-    const bool active = i < a.n;
-    const int64_t ii = active ? i : a.n - 1;
-    const int64_t n = a.n;
-    const T xi = load_x<T>(a, 0, ii), yi = load_x<T>(a, 1, ii), zi = load_x<T>(a, 2, ii);
-    T uix = T(0), uiy = T(0), uiz = T(0);
-    if (DL && SUB) {
-        uix = T(a.dl_dens[ii]);
-        uiy = T(a.dl_dens[n + ii]);
-        uiz = T(a.dl_dens[2 * n + ii]);
-    }
-    const T id = T(a.inv_delta), id2 = id * id;
-    const T rc2 = T(a.rc2);
-
+struct StokesOp {
+    static constexpr int C = 3;
+    static constexpr int TD = DL ? kTile : 1, TS = SL ? kTile : 1;
+    struct Smem {
+        T x[kTile], y[kTile], z[kTile];
+        T nx[TD], ny[TD], nz[TD], ux[TD], uy[TD], uz[TD];
+        T fx[TS], fy[TS], fz[TS];
+    };
+    T xi, yi, zi, uix = T(0), uiy = T(0), uiz = T(0);
     double ax = 0.0, ay = 0.0, az = 0.0;
-    const int64_t j0 = (int64_t)split * a.chunk;
-    const int64_t j1 = j0 + a.chunk < n ? j0 + a.chunk : n;
-    for (int64_t base = j0; base < j1; base += kTile) {
-        const int cnt = (int)((j1 - base) < kTile ? (j1 - base) : kTile);
-        __syncthreads();
-        for (int t = threadIdx.x; t < cnt; t += kTPB) {
-            const int64_t j = base + t;
-            sx[t] = load_x<T>(a, 0, j);
-            sy[t] = load_x<T>(a, 1, j);
-            sz[t] = load_x<T>(a, 2, j);
-            const double wj = a.w[j];
-            const double nx = a.nrm[j], ny = a.nrm[n + j], nz = a.nrm[2 * n + j];
-            double ux = 0.0, uy = 0.0, uz = 0.0;
-            if (DL || SLIP) {
-                ux = a.dl_dens[j];
-                uy = a.dl_dens[n + j];
-                uz = a.dl_dens[2 * n + j];
-            }
-            if (DL) {
-                const double s = a.c_dl * wj;
-                snx[t] = T(s * nx);
-                sny[t] = T(s * ny);
-                snz[t] = T(s * nz);
-                sux[t] = T(ux);
-                suy[t] = T(uy);
-                suz[t] = T(uz);
-            }
-            if (SL) {
-                double fx, fy, fz;
-                if (SLIP) {
-                    const double un = ux * nx + uy * ny + uz * nz;
-                    fx = a.slip_beta * (ux - un * nx);
-                    fy = a.slip_beta * (uy - un * ny);
-                    fz = a.slip_beta * (uz - un * nz);
-                } else {
-                    fx = a.sl_dens[j];
-                    fy = a.sl_dens[n + j];
-                    fz = a.sl_dens[2 * n + j];
-                }
-                const double s = a.c_sl * wj;
-                sfx[t] = T(s * fx);
-                sfy[t] = T(s * fy);
-                sfz[t] = T(s * fz);
-            }
+    T tx = T(0), ty = T(0), tz = T(0);
+
+    __device__ __forceinline__ void init(const KArgs& a, int64_t i) {
+        xi = load_x<T>(a, 0, i);
+        yi = load_x<T>(a, 1, i);
+        zi = load_x<T>(a, 2, i);
+        if (DL && SUB) {
+            uix = T(dens_at(a.dl_dens, a.n, 0, i));
+            uiy = T(dens_at(a.dl_dens, a.n, 1, i));
+            uiz = T(dens_at(a.dl_dens, a.n, 2, i));
         }
-        __syncthreads();
-        T tx = T(0), ty = T(0), tz = T(0);
-        for (int jj = 0; jj < cnt; ++jj) {
-            const T dx = xi - sx[jj], dy = yi - sy[jj], dz = zi - sz[jj];
-            const T r2 = dx * dx + dy * dy + dz * dz;
-            const T inv_r = rsq(r2);
-            const T ir2 = inv_r * inv_r;
-            T k1 = inv_r, k2, k3 = inv_r * ir2, k4 = k3 * ir2;
-            if (r2 < rc2) near_factors<T, SL, false, SL, DL>(r2, inv_r, id, id2, k1, k2, k3, k4);
-            if (DL) {
-                const T ux = sux[jj] - uix, uy = suy[jj] - uiy, uz = suz[jj] - uiz;
-                const T ud = ux * dx + uy * dy + uz * dz;
-                const T dn = dx * snx[jj] + dy * sny[jj] + dz * snz[jj];
-                const T c = ud * dn * k4;
-                tx += c * dx;
-                ty += c * dy;
-                tz += c * dz;
-            }
-            if (SL) {
-                const T fx = sfx[jj], fy = sfy[jj], fz = sfz[jj];
-                const T c = (dx * fx + dy * fy + dz * fz) * k3;
-                tx += fx * k1 + c * dx;
-                ty += fy * k1 + c * dy;
-                tz += fz * k1 + c * dz;
-            }
+    }
+    __device__ __forceinline__ void load(Smem& s, int t, int64_t j, const KArgs& a) const {
+        const int64_t np = a.npad;
+        s.x[t] = load_x<T>(a, 0, j);
+        s.y[t] = load_x<T>(a, 1, j);
+        s.z[t] = load_x<T>(a, 2, j);
+        const double wj = a.w[j];
+        const double nx = a.nrm[j], ny = a.nrm[np + j], nz = a.nrm[2 * np + j];
+        double ux = 0.0, uy = 0.0, uz = 0.0;
+        if (DL || SLIP) {
+            ux = dens_at(a.dl_dens, a.n, 0, j);
+            uy = dens_at(a.dl_dens, a.n, 1, j);
+            uz = dens_at(a.dl_dens, a.n, 2, j);
         }
+        if (DL) {
+            const double c = a.c_dl * wj;
+            s.nx[t] = T(c * nx);
+            s.ny[t] = T(c * ny);
+            s.nz[t] = T(c * nz);
+            s.ux[t] = T(ux);
+            s.uy[t] = T(uy);
+            s.uz[t] = T(uz);
+        }
+        if (SL) {
+            double fx, fy, fz;
+            if (SLIP) {
+                const double un = ux * nx + uy * ny + uz * nz;
+                fx = a.slip_beta * (ux - un * nx);
+                fy = a.slip_beta * (uy - un * ny);
+                fz = a.slip_beta * (uz - un * nz);
+            } else {
+                fx = dens_at(a.sl_dens, a.n, 0, j);
+                fy = dens_at(a.sl_dens, a.n, 1, j);
+                fz = dens_at(a.sl_dens, a.n, 2, j);
+            }
+            const double c = a.c_sl * wj;
+            s.fx[t] = T(c * fx);
+            s.fy[t] = T(c * fy);
+            s.fz[t] = T(c * fz);
+        }
+    }
+    template <bool NEAR>
+    __device__ __forceinline__ void pair(const Smem& s, int jj, T id, T id2, T rc2) {
+        const T dx = xi - s.x[jj], dy = yi - s.y[jj], dz = zi - s.z[jj];
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const T inv_r = rsq(r2);
+        const T ir2 = inv_r * inv_r;
+        T k1 = inv_r, k2, k3 = inv_r * ir2, k4 = k3 * ir2;
+        if (NEAR && r2 < rc2) near_factors<T, SL, false, SL, DL>(r2, inv_r, id, id2, k1, k2, k3, k4);
+        if (DL) {
+            const T ux = s.ux[jj] - uix, uy = s.uy[jj] - uiy, uz = s.uz[jj] - uiz;
+            const T ud = ux * dx + uy * dy + uz * dz;
+            const T dn = dx * s.nx[jj] + dy * s.ny[jj] + dz * s.nz[jj];
+            const T c = ud * dn * k4;
+            tx += c * dx;
+            ty += c * dy;
+            tz += c * dz;
+        }
+        if (SL) {
+            const T fx = s.fx[jj], fy = s.fy[jj], fz = s.fz[jj];
+            const T c = (dx * fx + dy * fy + dz * fz) * k3;
+            tx += fx * k1 + c * dx;
+            ty += fy * k1 + c * dy;
+            tz += fz * k1 + c * dz;
+        }
+    }
+    __device__ __forceinline__ void flush() {
         ax += (double)tx;
         ay += (double)ty;
         az += (double)tz;
+        tx = ty = tz = T(0);
     }
-    if (active) {
-        double* o = a.partial + (int64_t)split * 3 * n;
+    __device__ __forceinline__ void store(const KArgs& a, int slot, int64_t i) const {
+        double* o = a.partial + (int64_t)slot * 3 * a.n;
         o[i] = ax;
-        o[n + i] = ay;
-        o[2 * n + i] = az;
+        o[a.n + i] = ay;
+        o[2 * a.n + i] = az;
     }
+};
+
+// Far-field pass: block (b, split) sums target tile b against every tile of
+// its split's range whose pairs are all beyond the cutoff (mask 0).  No
+// smoothing code is compiled in: every pair uses the plain 1/r^p kernels.
+template <class Op, typename T>
+__global__ __launch_bounds__(kTPB) void far_pairs(KArgs a) {
+    __shared__ typename Op::Smem sm;
+    const int split = blockIdx.x % a.nsplit;
+    const int b = blockIdx.x / a.nsplit;
+    const int64_t i = (int64_t)b * kTPB + threadIdx.x;  // < npad
+    Op op;
+    op.init(a, i);
+    const T id = T(a.inv_delta), id2 = id * id, rc2 = T(a.rc2);
+    const int t0 = split * a.tiles_per_split;
+    const int t1 = t0 + a.tiles_per_split < a.ntiles ? t0 + a.tiles_per_split : a.ntiles;
+    const uint8_t* row = a.mask + (int64_t)b * a.ntiles;
+    for (int t = t0; t < t1; ++t) {
+        if (row[t]) continue;  // block-uniform
+        __syncthreads();
+        op.load(sm, threadIdx.x, (int64_t)t * kTile + threadIdx.x, a);
+        __syncthreads();
+#pragma unroll 8
+        for (int jj = 0; jj < kTile; ++jj) op.template pair<false>(sm, jj, id, id2, rc2);
+        op.flush();
+    }
+    if (i < a.n) op.store(a, split, i);
+}
+
+// Near-field pass: block (b, split) walks the near tiles of row b (mask 1) in
+// order, cut into units of kNearUnit sources, and takes every nsplit-th unit.
+template <class Op, typename T>
+__global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
+    __shared__ typename Op::Smem sm;
+    const int split = blockIdx.x % a.nsplit;
+    const int b = blockIdx.x / a.nsplit;
+    const int64_t i = (int64_t)b * kTPB + threadIdx.x;
+    Op op;
+    op.init(a, i);
+    const T id = T(a.inv_delta), id2 = id * id, rc2 = T(a.rc2);
+    const uint8_t* row = a.mask + (int64_t)b * a.ntiles;
+    constexpr int kUnits = kTile / kNearUnit;
+    int rank = 0;
+    const int lane = threadIdx.x & 63;
+    for (int c0 = 0; c0 < a.ntiles; c0 += 64) {
+        const bool f = (c0 + lane < a.ntiles) && row[c0 + lane];
+        uint64_t bal = __ballot(f);  // identical in every wave of the block
+        while (bal) {
+            const int t = c0 + __ffsll((long long)bal) - 1;
+            bal &= bal - 1;
+            for (int q = 0; q < kUnits; ++q) {
+                if ((rank * kUnits + q) % a.nsplit != split) continue;
+                __syncthreads();
+                if (threadIdx.x < kNearUnit)
+                    op.load(sm, threadIdx.x, (int64_t)t * kTile + q * kNearUnit + threadIdx.x, a);
+                __syncthreads();
+                for (int jj = 0; jj < kNearUnit; ++jj) op.template pair<true>(sm, jj, id, id2, rc2);
+                op.flush();
+            }
+            ++rank;
+        }
+    }
+    if (i < a.n) op.store(a, a.nsplit + split, i);
 }
 
 // out_i = sum_s partial[s][c][i] + base_scale*base + comp_scale*(*comp)*vecfac + add[c]
 template <int C>
-__global__ void epilogue(int64_t n, int nsplit, const double* __restrict__ partial,
+__global__ void epilogue(int64_t n, int nslots, const double* __restrict__ partial,
                          const double* __restrict__ base, double base_scale,
                          const double* __restrict__ comp, double comp_scale,
                          const double* __restrict__ nrm, double add0, double add1, double add2,
@@ -299,7 +364,7 @@ __global__ void epilogue(int64_t n, int nsplit, const double* __restrict__ parti
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         double v = 0.0;
-        for (int s = 0; s < nsplit; ++s) v += partial[((int64_t)s * C + c) * n + i];
+        for (int s = 0; s < nslots; ++s) v += partial[((int64_t)s * C + c) * n + i];
         if (base) v += base_scale * base[c * n + i];
         if (comp) v += cs * (C == 3 ? nrm[c * n + i] : 1.0);
         v += (c == 0 ? add0 : (c == 1 ? add1 : add2));
@@ -310,12 +375,15 @@ __global__ void epilogue(int64_t n, int nsplit, const double* __restrict__ parti
 KArgs make_args(const Plan& P, const PassDesc& d, int nsplit, double cut) {
     KArgs a;
     a.n = P.n;
+    a.npad = P.npad;
+    a.ntiles = P.ntiles;
     a.nsplit = nsplit;
-    a.chunk = (P.n + nsplit - 1) / nsplit;
-    a.x = P.x;
-    a.nrm = P.nrm;
-    a.w = P.w;
-    a.x32 = P.x32;
+    a.tiles_per_split = (P.ntiles + nsplit - 1) / nsplit;
+    a.x = P.px;
+    a.nrm = P.pn;
+    a.w = P.pw;
+    a.x32 = P.px32;
+    a.mask = d.mixed ? P.mask32 : P.mask64;
     a.dl_dens = d.dl_dens;
     a.sl_dens = d.sl_dens;
     a.c_dl = d.c_dl;
@@ -325,6 +393,15 @@ KArgs make_args(const Plan& P, const PassDesc& d, int nsplit, double cut) {
     a.rc2 = (cut * P.delta) * (cut * P.delta);
     a.partial = P.partial;
     return a;
+}
+
+template <class Op, typename T>
+void launch_pair_kernels(const KArgs& a, hipStream_t st) {
+    const dim3 grid((unsigned)((int64_t)a.ntiles * a.nsplit));
+    hipLaunchKernelGGL((far_pairs<Op, T>), grid, dim3(kTPB), 0, st, a);
+    SDBIE_LAUNCHED();
+    hipLaunchKernelGGL((near_pairs<Op, T>), grid, dim3(kTPB), 0, st, a);
+    SDBIE_LAUNCHED();
 }
 
 }  // namespace
@@ -337,37 +414,39 @@ int choose_splits(int64_t n) {
     return (int)(s < 1 ? 1 : s);
 }
 
+// The smoothing cutoff rho_cut of a pass is the Stokes one (the larger) for
+// both families, matching the tile masks built at staging.
 void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
     const int S = choose_splits(P.n);
-    const int64_t tblocks = (P.n + kTPB - 1) / kTPB;
-    const dim3 grid((unsigned)(tblocks * S));
-    const double cut = d.mixed ? (double)SDBIE_RHO_CUT_LAPLACE_F32 : SDBIE_RHO_CUT_LAPLACE_F64;
+    const double cut = d.mixed ? (double)SDBIE_RHO_CUT_STOKES_F32 : SDBIE_RHO_CUT_STOKES_F64;
     const KArgs a = make_args(P, d, S, cut);
-#define SDBIE_LAP(T, DL, SL, SUB) hipLaunchKernelGGL((laplace_pairs<T, DL, SL, SUB>), grid, dim3(kTPB), 0, st, a)
     const int code = (d.dl ? 1 : 0) | (d.sl ? 2 : 0) | (d.sub ? 4 : 0);
-    if (!d.mixed) {
-        switch (code) {
-            case 1: SDBIE_LAP(double, true, false, false); break;
-            case 5: SDBIE_LAP(double, true, false, true); break;
-            case 2: case 6: SDBIE_LAP(double, false, true, false); break;
-            case 3: SDBIE_LAP(double, true, true, false); break;
-            case 7: SDBIE_LAP(double, true, true, true); break;
-            default: throw Error(SDBIE_ERR_ARG, "empty Laplace pass");
+    {
+        ProfScope prof(prof_variant(0, d.mixed, d.sl && !d.dl ? 2 : code), (double)P.n * (double)P.n, st);
+#define SDBIE_LAP(T, DL, SL, SUB) launch_pair_kernels<LaplaceOp<T, DL, SL, SUB>, T>(a, st)
+        if (!d.mixed) {
+            switch (code) {
+                case 1: SDBIE_LAP(double, true, false, false); break;
+                case 5: SDBIE_LAP(double, true, false, true); break;
+                case 2: case 6: SDBIE_LAP(double, false, true, false); break;
+                case 3: SDBIE_LAP(double, true, true, false); break;
+                case 7: SDBIE_LAP(double, true, true, true); break;
+                default: throw Error(SDBIE_ERR_ARG, "empty Laplace pass");
+            }
+        } else {
+            switch (code) {
+                case 1: SDBIE_LAP(float, true, false, false); break;
+                case 5: SDBIE_LAP(float, true, false, true); break;
+                case 2: case 6: SDBIE_LAP(float, false, true, false); break;
+                case 3: SDBIE_LAP(float, true, true, false); break;
+                case 7: SDBIE_LAP(float, true, true, true); break;
+                default: throw Error(SDBIE_ERR_ARG, "empty Laplace pass");
+            }
         }
-    } else {
-        switch (code) {
-            case 1: SDBIE_LAP(float, true, false, false); break;
-            case 5: SDBIE_LAP(float, true, false, true); break;
-            case 2: case 6: SDBIE_LAP(float, false, true, false); break;
-            case 3: SDBIE_LAP(float, true, true, false); break;
-            case 7: SDBIE_LAP(float, true, true, true); break;
-            default: throw Error(SDBIE_ERR_ARG, "empty Laplace pass");
-        }
-    }
 #undef SDBIE_LAP
-    SDBIE_LAUNCHED();
+    }
     const double* add = d.add_const;
-    hipLaunchKernelGGL((epilogue<1>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P.n, S,
+    hipLaunchKernelGGL((epilogue<1>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P.n, 2 * S,
                        (const double*)P.partial, d.base, d.base_scale, d.comp, d.comp_scale,
                        (const double*)P.nrm, add ? add[0] : 0.0, 0.0, 0.0, d.out,
                        d.scatter ? (const int32_t*)P.perm : nullptr);
@@ -379,37 +458,36 @@ void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
 
 void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
     const int S = choose_splits(P.n);
-    const int64_t tblocks = (P.n + kTPB - 1) / kTPB;
-    const dim3 grid((unsigned)(tblocks * S));
     const double cut = d.mixed ? (double)SDBIE_RHO_CUT_STOKES_F32 : SDBIE_RHO_CUT_STOKES_F64;
     const KArgs a = make_args(P, d, S, cut);
-#define SDBIE_STO(T, DL, SL, SUB, SLIP) \
-    hipLaunchKernelGGL((stokes_pairs<T, DL, SL, SUB, SLIP>), grid, dim3(kTPB), 0, st, a)
     const bool slip = d.sl && d.slip_beta != 0.0 && d.sl_dens == nullptr;
     const int code = (d.dl ? 1 : 0) | (d.sl ? 2 : 0) | (d.sub ? 4 : 0) | (slip ? 8 : 0);
-    if (!d.mixed) {
-        switch (code) {
-            case 1: SDBIE_STO(double, true, false, false, false); break;
-            case 5: SDBIE_STO(double, true, false, true, false); break;
-            case 2: SDBIE_STO(double, false, true, false, false); break;
-            case 7: SDBIE_STO(double, true, true, true, false); break;
-            case 15: SDBIE_STO(double, true, true, true, true); break;
-            default: throw Error(SDBIE_ERR_ARG, "unsupported Stokes pass");
+    {
+        ProfScope prof(prof_variant(1, d.mixed, code), (double)P.n * (double)P.n, st);
+#define SDBIE_STO(T, DL, SL, SUB, SLIP) launch_pair_kernels<StokesOp<T, DL, SL, SUB, SLIP>, T>(a, st)
+        if (!d.mixed) {
+            switch (code) {
+                case 1: SDBIE_STO(double, true, false, false, false); break;
+                case 5: SDBIE_STO(double, true, false, true, false); break;
+                case 2: SDBIE_STO(double, false, true, false, false); break;
+                case 7: SDBIE_STO(double, true, true, true, false); break;
+                case 15: SDBIE_STO(double, true, true, true, true); break;
+                default: throw Error(SDBIE_ERR_ARG, "unsupported Stokes pass");
+            }
+        } else {
+            switch (code) {
+                case 1: SDBIE_STO(float, true, false, false, false); break;
+                case 5: SDBIE_STO(float, true, false, true, false); break;
+                case 2: SDBIE_STO(float, false, true, false, false); break;
+                case 7: SDBIE_STO(float, true, true, true, false); break;
+                case 15: SDBIE_STO(float, true, true, true, true); break;
+                default: throw Error(SDBIE_ERR_ARG, "unsupported Stokes pass");
+            }
         }
-    } else {
-        switch (code) {
-            case 1: SDBIE_STO(float, true, false, false, false); break;
-            case 5: SDBIE_STO(float, true, false, true, false); break;
-            case 2: SDBIE_STO(float, false, true, false, false); break;
-            case 7: SDBIE_STO(float, true, true, true, false); break;
-            case 15: SDBIE_STO(float, true, true, true, true); break;
-            default: throw Error(SDBIE_ERR_ARG, "unsupported Stokes pass");
-        }
-    }
 #undef SDBIE_STO
-    SDBIE_LAUNCHED();
+    }
     const double* add = d.add_const;
-    hipLaunchKernelGGL((epilogue<3>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P.n, S,
+    hipLaunchKernelGGL((epilogue<3>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P.n, 2 * S,
                        (const double*)P.partial, d.base, d.base_scale, d.comp, d.comp_scale,
                        (const double*)P.nrm, add ? add[0] : 0.0, add ? add[1] : 0.0, add ? add[2] : 0.0,
                        d.out, d.scatter ? (const int32_t*)P.perm : nullptr);

@@ -1,0 +1,120 @@
+// Optional kernel timing: a HIP event pair around every pair-sum kernel.
+//
+// When enabled (sdbie_profile_enable(1)), each launch of a pair-sum kernel
+// records an event before and after it on the stream it is launched on.
+// sdbie_profile_read() waits for the recorded events and reports, per kernel
+// variant, the launch count, the summed kernel time, the pair evaluations and
+// the algorithmic flop count per pair (far field: FMA = 2, add/mul = 1,
+// each rsqrt = 1; the near-field smoothing is not counted).
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace sdbie {
+namespace {
+
+struct Rec {
+    int variant;
+    double pairs;
+    hipEvent_t a, b;
+};
+
+std::mutex g_mu;
+bool g_on = false;
+std::vector<Rec> g_recs;
+
+}  // namespace
+
+// variant = family * 64 + mixed * 32 + code
+int prof_variant(int family, bool mixed, int code) { return family * 64 + (mixed ? 32 : 0) + code; }
+
+std::string prof_name(int v) {
+    const int family = v / 64, mixed = (v / 32) & 1, code = v & 31;
+    std::string s = family == 0 ? "laplace_pairs<" : "stokes_pairs<";
+    s += mixed ? "f32" : "f64";
+    if (code & 1) s += ",DL";
+    if (code & 2) s += ",SL";
+    if (code & 4) s += ",SUB";
+    if (code & 8) s += ",SLIP";
+    return s + ">";
+}
+
+double flops_per_pair(int v) {
+    const int family = v / 64, code = v & 31;
+    const bool dl = code & 1, sl = code & 2, sub = code & 4;
+    // common: D (3), r^2 (1 mul + 2 fma = 5), rsqrt (1)
+    double f = 9.0;
+    if (family == 0) {
+        if (dl) f += 2 + 5 + 4;       // k2 = inv_r^3 (2), D.n (5), (q_j - q_i) dn k2 + acc (4)
+        if (sl) f += 2;               // acc += g k1
+    } else {
+        f += 1 + (sl ? 1 : 0) + (dl ? 1 : 0);  // ir2, k3, k4
+        if (dl) f += (sub ? 3 : 0) + 5 + 5 + 2 + 6;  // u_j - u_i, (u.D), (D.n), c, acc += c D
+        if (sl) f += 5 + 1 + 12;                     // D.f, * k3, acc += f k1 + c D
+    }
+    return f;
+}
+
+ProfScope::ProfScope(int variant, double pairs, hipStream_t s) : s_(s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!g_on) return;
+    Rec r{variant, pairs, nullptr, nullptr};
+    if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return;
+    if (hipEventRecord(r.a, s) != hipSuccess) return;
+    g_recs.push_back(r);
+    idx_ = (long)g_recs.size() - 1;
+}
+
+ProfScope::~ProfScope() {
+    if (idx_ < 0) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (idx_ < (long)g_recs.size()) (void)hipEventRecord(g_recs[idx_].b, s_);
+}
+
+}  // namespace sdbie
+
+extern "C" {
+
+int sdbie_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(sdbie::g_mu);
+    for (auto& r : sdbie::g_recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    sdbie::g_recs.clear();
+    sdbie::g_on = on != 0;
+    return SDBIE_OK;
+}
+
+int sdbie_profile_read(sdbie_kernel_stat* out, int max, int* count) {
+    std::lock_guard<std::mutex> lk(sdbie::g_mu);
+    if (!count || (max > 0 && !out)) return SDBIE_ERR_ARG;
+    std::vector<sdbie_kernel_stat> acc;
+    std::vector<int> ids;
+    for (auto& r : sdbie::g_recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return SDBIE_ERR_DEVICE;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return SDBIE_ERR_DEVICE;
+        size_t k = 0;
+        while (k < ids.size() && ids[k] != r.variant) ++k;
+        if (k == ids.size()) {
+            ids.push_back(r.variant);
+            sdbie_kernel_stat st;
+            std::memset(&st, 0, sizeof(st));
+            std::strncpy(st.name, sdbie::prof_name(r.variant).c_str(), sizeof(st.name) - 1);
+            st.flops_per_pair = sdbie::flops_per_pair(r.variant);
+            acc.push_back(st);
+        }
+        acc[k].launches += 1;
+        acc[k].ms += ms;
+        acc[k].pairs += r.pairs;
+    }
+    *count = (int)acc.size();
+    for (int i = 0; i < (int)acc.size() && i < max; ++i) out[i] = acc[i];
+    return SDBIE_OK;
+}
+
+}  // extern "C"

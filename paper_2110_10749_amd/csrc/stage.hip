@@ -9,7 +9,11 @@
 // key per node (10 bits per axis), key<<32 | index sorted by a bitonic network
 // over the next power of two (padding keys = UINT64_MAX; keys are unique, so
 // the order is deterministic), then gather of x, n, w into sorted double
-// arrays, float copies of x, and the weighted normals w n.
+// arrays and the weighted normals w n; copies padded to whole tiles of kTile
+// nodes (double and float) for the pair kernels; per-tile bounding boxes and
+// the near-field masks of tile pairs (box distance below rho_cut delta, one
+// mask for the double cutoff and one for the float cutoff).
+#include "smoothing_coeffs.h"
 #include "solver.h"
 
 namespace sdbie {
@@ -87,23 +91,75 @@ __global__ void k_bitonic(uint64_t* __restrict__ keys, int64_t npow2, int64_t j,
 __global__ void k_stage(int64_t n, const uint64_t* __restrict__ keys, const double* __restrict__ x,
                         const double* __restrict__ nrm, const double* __restrict__ w, int32_t* __restrict__ perm,
                         double* __restrict__ xs, double* __restrict__ ns, double* __restrict__ wsrt,
-                        double* __restrict__ wn, float* __restrict__ x32, float* __restrict__ n32,
-                        float* __restrict__ w32) {
+                        double* __restrict__ wn) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int64_t o = (int64_t)(keys[k] & 0xffffffffull);
     perm[k] = (int32_t)o;
     const double wk = w[o];
     wsrt[k] = wk;
-    w32[k] = (float)wk;
     for (int c = 0; c < 3; ++c) {
         const double xv = x[c * n + o], nv = nrm[c * n + o];
         xs[c * n + k] = xv;
         ns[c * n + k] = nv;
         wn[c * n + k] = wk * nv;
-        x32[c * n + k] = (float)xv;
-        n32[c * n + k] = (float)nv;
     }
+}
+
+// padded copies for the pair kernels: nodes k >= n sit at a point `far`
+// outside the bounding box (10 extents away) with zero weight and normal
+__global__ void k_pad(int64_t n, int64_t npad, const double* __restrict__ xs, const double* __restrict__ ns,
+                      const double* __restrict__ ws, const double* __restrict__ bb, double* __restrict__ px,
+                      double* __restrict__ pn, double* __restrict__ pw, float* __restrict__ px32) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= npad) return;
+    const double ext = fmax(fmax(bb[1] - bb[0], bb[3] - bb[2]), bb[5] - bb[4]);
+    for (int c = 0; c < 3; ++c) {
+        const double xv = k < n ? xs[c * n + k] : bb[2 * c + 1] + 10.0 * ext + 1.0;
+        px[c * npad + k] = xv;
+        pn[c * npad + k] = k < n ? ns[c * n + k] : 0.0;
+        px32[c * npad + k] = (float)xv;
+    }
+    pw[k] = k < n ? ws[k] : 0.0;
+}
+
+// bounding box of each tile of kTile consecutive (sorted) real nodes
+__global__ __launch_bounds__(256) void k_tile_boxes(int64_t n, const double* __restrict__ xs,
+                                                     double* __restrict__ boxes) {
+    __shared__ double sh[6][256];
+    const int64_t k = (int64_t)blockIdx.x * kTile + threadIdx.x;
+    for (int c = 0; c < 3; ++c) {
+        const double v = k < n ? xs[c * n + k] : NAN;
+        sh[2 * c][threadIdx.x] = k < n ? v : INFINITY;
+        sh[2 * c + 1][threadIdx.x] = k < n ? v : -INFINITY;
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int c = 0; c < 3; ++c) {
+                sh[2 * c][threadIdx.x] = fmin(sh[2 * c][threadIdx.x], sh[2 * c][threadIdx.x + s]);
+                sh[2 * c + 1][threadIdx.x] = fmax(sh[2 * c + 1][threadIdx.x], sh[2 * c + 1][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) boxes[(int64_t)blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// mask[b][t] = 1 when the boxes of tiles b and t are closer than the cutoff
+__global__ void k_near_masks(int nt, const double* __restrict__ boxes, double rc64, double rc32,
+                             uint8_t* __restrict__ m64, uint8_t* __restrict__ m32) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)nt * nt) return;
+    const int64_t b = idx / nt, t = idx % nt;
+    const double* A = boxes + b * 6;
+    const double* B = boxes + t * 6;
+    double d2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double gap = fmax(0.0, fmax(A[2 * c] - B[2 * c + 1], B[2 * c] - A[2 * c + 1]));
+        d2 += gap * gap;
+    }
+    m64[idx] = d2 < rc64 * rc64 ? 1 : 0;
+    m32[idx] = d2 < rc32 * rc32 ? 1 : 0;
 }
 
 }  // namespace
@@ -133,7 +189,20 @@ void stage_surface(Plan& P, const sdbie_surface* s, hipStream_t st) {
             SDBIE_LAUNCHED();
         }
     hipLaunchKernelGGL(k_stage, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, (const uint64_t*)P.keys,
-                       s->x, s->nrm, s->w, P.perm, P.x, P.nrm, P.w, P.wn, P.x32, P.n32, P.w32);
+                       s->x, s->nrm, s->w, P.perm, P.x, P.nrm, P.w, P.wn);
+    SDBIE_LAUNCHED();
+    hipLaunchKernelGGL(k_pad, dim3((unsigned)((P.npad + 255) / 256)), dim3(256), 0, st, n, P.npad,
+                       (const double*)P.x, (const double*)P.nrm, (const double*)P.w, (const double*)bb, P.px, P.pn,
+                       P.pw, P.px32);
+    SDBIE_LAUNCHED();
+    hipLaunchKernelGGL(k_tile_boxes, dim3((unsigned)P.ntiles), dim3(kTile), 0, st, n, (const double*)P.x, P.boxes);
+    SDBIE_LAUNCHED();
+    // cutoffs with a relative margin of 1e-6 (the far kernels assume rho >= rho_cut)
+    const double rc64 = SDBIE_RHO_CUT_STOKES_F64 * P.delta * (1.0 + 1e-6);
+    const double rc32 = SDBIE_RHO_CUT_STOKES_F32 * P.delta * (1.0 + 1e-6);
+    const int64_t nt2 = (int64_t)P.ntiles * P.ntiles;
+    hipLaunchKernelGGL(k_near_masks, dim3((unsigned)((nt2 + 255) / 256)), dim3(256), 0, st, P.ntiles,
+                       (const double*)P.boxes, rc64, rc32, P.mask64, P.mask32);
     SDBIE_LAUNCHED();
     dev_dot(P, P.w, nullptr, n, P.scal + kScalStage + 8, st);
     P.area = host_read_scalar(P.scal + kScalStage + 8, st);
