@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_NONPACKED = 256 * 64 * 2 * 2.4e9 / 1e12   # 78.6 TFLOP/s: 256 CU x 64 lanes x FMA x 2.4 GHz
 PEAK_FP32_PACKED = 157.3                              # published, needs packed FP32 (not used here)
 PEAK_FP64 = 78.6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def log(*a):
@@ -73,6 +74,31 @@ def cpu_baseline(S, delta, budget_s: float = 15.0):
                       f"on {M} of {S.N} target rows x all {S.N} sources, FP64, {dt:.1f} s"}
 
 
+def kernel_source_digest() -> str:
+    """Digest of the pair-kernel sources (traffic counters are only valid for them)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("pair_kernels.hip", "smoothing_coeffs.h", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2110_10749_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel_name: str, n: int):
+    """HBM bytes per launch of the dominant pass from rocprofv3 --pmc FETCH_SIZE /
+    WRITE_SIZE runs (profiles/traffic.json), scaled by the same counters on a plain
+    copy of known size; null when absent or when the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_digest") != kernel_source_digest() or t.get("N") != n:
+        return None
+    ent = t.get("kernels", {}).get(kernel_name)
+    return None if ent is None else ent.get("bytes_per_launch")
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +107,9 @@ def main() -> int:
     ap.add_argument("--inv-h", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (calibrates the HBM "
+                         "byte counters of a profiler) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -89,6 +118,16 @@ def main() -> int:
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        n = args.copy_calibration // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 8 * n, "launches": 3}), flush=True)
+        return 0
 
     import paper_2110_10749_amd as sd
     from workloads import exact, surfaces
@@ -139,7 +178,7 @@ def main() -> int:
     is32 = "f32" in dom["name"]
     peak = PEAK_FP32_NONPACKED if is32 else PEAK_FP64
     roofline = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": None,
+                "frac": achieved / peak, "traffic": measured_traffic(dom["name"], S.N),
                 "kernel": dom["name"], "avg_ms": avg_ms, "launches_per_step": dom["launches"] / args.steps,
                 "flops_per_pair": dom["flops_per_pair"], "pairs_per_launch": pairs_per_launch,
                 "peak_basis": ("non-packed fp32 FMA: 256 CU x 64 lanes x 2 flop x 2.4 GHz (packed fp32 "

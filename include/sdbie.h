@@ -97,6 +97,9 @@ typedef struct {
     int prec;           /* sdbie_precision of the pair sums in the solves */
     double tol_mixed;   /* SDBIE_MIXED: relative tolerance of each float-pair correction solve */
     int refine_max;     /* SDBIE_MIXED: maximum refinement steps */
+    int mixed_mode;     /* SDBIE_MIXED with outer = 1: 0 = refine every local solve (double
+                           residual of the Darcy / Stokes equation); 1 = refine the coupled
+                           system (double residual of both equations, float-pair D-N corrections) */
 } sdbie_opts;
 
 typedef struct {
@@ -114,7 +117,7 @@ typedef struct sdbie_plan_s* sdbie_plan;
 
 /* Fill `o` with the defaults: tol_gmres 1e-10, tol_ddm 1e-8, theta 0.5,
  * maxit_gmres 500, restart 50, maxit_ddm 200, outer 1, slip 0, prec FP64,
- * tol_mixed 1e-5, refine_max 8. */
+ * tol_mixed 1e-5, refine_max 8, mixed_mode 0. */
 void sdbie_default_opts(sdbie_opts* o);
 
 /* Bytes of device workspace a plan for n nodes (1 <= n <= 2^23) and GMRES
@@ -170,6 +173,20 @@ int stokes_solve(sdbie_plan plan, const sdbie_params* prm, const double U[3], co
 int ddm_solve(sdbie_plan plan, const sdbie_params* prm, const double U[3], const double* f_extra,
               double* p, double* u, double drag[3], const sdbie_opts* opts, sdbie_info* info,
               void* stream);
+
+/* Adjoint of ddm_solve (not in the paper): gradient of J = dJ_ddrag . drag
+ * with respect to the node coordinates (device [3][n], normals and weights
+ * held fixed: the derivative of the discrete map), log K and alpha (host
+ * doubles).  p, u (device [n], [3][n], caller order) are the converged
+ * outputs of ddm_solve for the same plan, parameters, U and f_extra; only they
+ * are needed (no Krylov history).  The transposed coupled system is solved by
+ * the transposed interface iteration (interface GMRES to opts->tol_ddm, local
+ * GMRES to opts->tol_gmres) with double pairs; then one position-gradient
+ * pass.  Returns NOT_CONVERGED if a Krylov solve missed its tolerance. */
+int ddm_adjoint(sdbie_plan plan, const sdbie_params* prm, const double U[3], const double* f_extra,
+                const double* p, const double* u, const double dJ_ddrag[3], double* dJ_dx,
+                double* dJ_dlogK, double* dJ_dalpha, const sdbie_opts* opts, sdbie_info* info,
+                void* stream);
 
 /* Kernel timing (diagnostics).  While enabled, every pair-sum kernel launch
  * records a HIP event pair around the kernel on the stream it runs on.

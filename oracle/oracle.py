@@ -74,6 +74,7 @@ def lib():
         L.oracle_stokes_apply.argtypes = [i64, p, p, p, d, d, i32, p, i64, p, p]
         L.oracle_laplace_matrix.argtypes = [i64, p, p, p, d, i32, p]
         L.oracle_stokes_matrix.argtypes = [i64, p, p, p, d, d, i32, p]
+        L.oracle_coupled_xgrad.argtypes = [i64, p, p, p, d, d, d, p, p, p, p, p, p, p]
         L.oracle_num_threads.restype = i32
         L.oracle_num_threads.argtypes = []
         _lib = L
@@ -426,15 +427,8 @@ def ddm_solve(ops: Operators, prm: Params, U, f_extra=None, opts: Opts | None = 
     return p, u, drag(geo, f), info
 
 
-def coupled_dense_solve(geo: Geometry, prm: Params, U, f_extra=None):
-    """Brute force: the fixed point of the D-N map as one dense 4N system.
-
-    Each Darcy solve returns p = Pi pt with Abar_D pt = (mu/K) S_L[u.n] and
-    Pi = I - 1 w^T/|S| (weighted mean removed), so the fixed point solves
-    [ Abar_D             -(mu/K) S_L Nrm ] [pt]   [ 0              ]
-    [ -V Nhat Pi     Abar_S + V beta P_t ] [u ] = [ U - V[f_extra] ]
-    with Nrm u = u.n and Nhat p = p n.  Returns (p, u, drag).
-    """
+def _coupled_blocks(geo: Geometry, prm: Params):
+    """Dense blocks of the coupled system (see coupled_dense_solve)."""
     N = geo.N
     mu = prm.mu
     AD = laplace_matrix(geo, LDLS) + np.outer(np.ones(N), geo.w) / geo.area
@@ -456,6 +450,20 @@ def coupled_dense_solve(geo: Geometry, prm: Params, U, f_extra=None):
     M[:N, N:] = -(mu / prm.K) * SL @ Nrm
     M[N:, :N] = -V @ (Nhat @ Pi)
     M[N:, N:] = AS + prm.beta * V @ Ptau
+    return M, V, SL, Pi, Ptau, Nrm
+
+
+def coupled_dense_solve(geo: Geometry, prm: Params, U, f_extra=None, return_pt=False):
+    """Brute force: the fixed point of the D-N map as one dense 4N system.
+
+    Each Darcy solve returns p = Pi pt with Abar_D pt = (mu/K) S_L[u.n] and
+    Pi = I - 1 w^T/|S| (weighted mean removed), so the fixed point solves
+    [ Abar_D             -(mu/K) S_L Nrm ] [pt]   [ 0              ]
+    [ -V Nhat Pi     Abar_S + V beta P_t ] [u ] = [ U - V[f_extra] ]
+    with Nrm u = u.n and Nhat p = p n.  Returns (p, u, drag) [, pt].
+    """
+    N = geo.N
+    M, V, SL, Pi, Ptau, Nrm = _coupled_blocks(geo, prm)
     rhs = np.zeros(4 * N)
     U = np.asarray(U, dtype=np.float64)
     rhs[N:] = np.repeat(U, N)
@@ -465,4 +473,56 @@ def coupled_dense_solve(geo: Geometry, prm: Params, U, f_extra=None):
     p = Pi @ z[:N]
     u = z[N:].reshape(3, N)
     f = traction(geo, prm, p, u, f_extra)
-    return p, u, drag(geo, f)
+    out = (p, u, drag(geo, f))
+    return out + (z[:N],) if return_pt else out
+
+
+def coupled_dense_adjoint(geo: Geometry, prm: Params, U, dJ_dD, f_extra=None):
+    """Gradient of J = dJ_dD . drag by the adjoint of the coupled system.
+
+    Forward: F(z; theta) = M z - b = 0 with z = (pt, u) (coupled_dense_solve);
+    J = e . sum_j w_j f_j, f = -(Pi pt) n + beta P_tau u + f_extra.
+    Adjoint: M^T lam = dJ/dz; then dJ/dtheta = dJ/dtheta|_z - lam^T dF/dtheta:
+      log K:  dF1 = (mu/K) S_L[u.n],  dF2 = V[-(beta/2) P_tau u],  dJ = e.sum w (-(beta/2)) P_tau u
+      alpha:  dF2 = V[(beta/alpha) P_tau u],                       dJ = e.sum w (beta/alpha) P_tau u
+      x:      the pair sums only (normals and weights held fixed), oracle_coupled_xgrad.
+    Returns (dJ_dx (3, N), dJ_dlogK, dJ_dalpha, forward (p, u, drag)).
+    """
+    N = geo.N
+    e = np.asarray(dJ_dD, dtype=np.float64).reshape(3)
+    M, V, SL, Pi, Ptau, Nrm = _coupled_blocks(geo, prm)
+    rhs = np.zeros(4 * N)
+    rhs[N:] = np.repeat(np.asarray(U, dtype=np.float64), N)
+    if f_extra is not None:
+        rhs[N:] -= V @ f_extra.reshape(-1)
+    z = np.linalg.solve(M, rhs)
+    pt, u = z[:N], z[N:].reshape(3, N)
+    p = Pi @ pt
+    f = traction(geo, prm, p, u, f_extra)
+    D = drag(geo, f)
+    # dJ/dz
+    en = (e[:, None] * geo.n).sum(axis=0)
+    gJ = np.zeros(4 * N)
+    gJ[:N] = Pi.T @ (-geo.w * en)
+    gJ[N:] = (prm.beta * geo.w[None, :] * tangential(geo.n, np.repeat(e[:, None], N, axis=1))).reshape(-1)
+    lam = np.linalg.solve(M.T, gJ)
+    lam1, lam2 = lam[:N], lam[N:].reshape(3, N)
+    tu = tangential(geo.n, u)
+    v = (geo.n * u).sum(axis=0)
+    # log K
+    dF1 = (prm.mu / prm.K) * (SL @ v)
+    dF2 = V @ (-(prm.beta / 2) * tu).reshape(-1)
+    dJ = (e[:, None] * (geo.w[None, :] * (-(prm.beta / 2)) * tu)).sum()
+    dlogK = dJ - lam1 @ dF1 - lam[N:] @ dF2
+    # alpha
+    sa = prm.mu / math.sqrt(prm.K)
+    dF2a = V @ (sa * tu).reshape(-1)
+    dJa = (e[:, None] * (geo.w[None, :] * sa * tu)).sum()
+    dalpha = dJa - lam[N:] @ dF2a
+    # positions
+    grad = np.empty((3, N))
+    lib().oracle_coupled_xgrad(N, _ptr(geo.x), _ptr(geo.n), _ptr(geo.w), geo.delta, prm.mu, prm.K,
+                               _ptr(np.ascontiguousarray(pt)), _ptr(np.ascontiguousarray(v)),
+                               _ptr(np.ascontiguousarray(u)), _ptr(np.ascontiguousarray(f)),
+                               _ptr(np.ascontiguousarray(lam1)), _ptr(np.ascontiguousarray(lam2)), _ptr(grad))
+    return grad, dlogK, dalpha, (p, u, D)

@@ -284,6 +284,84 @@ void oracle_stokes_matrix(int64_t n, const double* x, const double* nrm, const d
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* position derivative of lambda^T F for the coupled system                 */
+/* ------------------------------------------------------------------------ */
+/* The coupled equations (unknowns pt, u; see oracle.py) are
+ *   F1_i = [A_D pt]_i + mean_w(pt) - (mu/K) S_L[v]_i,               v = u.n
+ *   F2_i = [A_S u]_i + (flux) n_i + V[f]_i - U,                      f = traction
+ * and only the pair sums depend on the node positions (normals and weights
+ * are held fixed).  With D = x_i - x_j the pair terms are
+ *   T1_ij = (1/4pi) w_j (pt_j - pt_i)(D.n_j) K2 + (mu/K)(1/4pi) w_j v_j K1
+ *   T2_ij = -(3/4pi) w_j ((u_j - u_i).D)(D.n_j) D K4 + (1/(8 pi mu)) w_j [f_j K1 + D (D.f_j) K3]
+ * with K1 = F1/delta, K2 = F2/delta^3, K3 = F3/delta^3, K4 = F4/delta^5 and
+ * grad_D K1 = -(F3/delta^3) D, grad_D K2 = -(G2/delta^5) D,
+ * grad_D K3 = -(3 F4/delta^5) D, grad_D K4 = -(G4/delta^7) D.
+ * With g_ij = grad_D [lam1_i T1_ij + lam2_i . T2_ij], the derivative of
+ * -(lam1.F1 + lam2.F2) with respect to x_m is
+ *   grad_m = -sum_j g_mj + sum_i g_im.
+ * Arrays: x, nrm, u, f, lam2, grad are [3][n]; pt, v, lam1 are [n]. */
+static void pair_grad(int64_t n, const double* x, const double* nrm, const double* w, double delta, double mu,
+                      double K, const double* pt, const double* v, const double* u, const double* f,
+                      const double* lam1, const double* lam2, int64_t i, int64_t j, double g[3])
+{
+    double d[3], nj[3], a[3], fj[3], lam[3];
+    for (int c = 0; c < 3; ++c) {
+        d[c] = x[c * n + i] - x[c * n + j];
+        nj[c] = nrm[c * n + j];
+        a[c] = u[c * n + j] - u[c * n + i];
+        fj[c] = f[c * n + j];
+        lam[c] = lam2[c * n + i];
+    }
+    const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double rho = r / delta;
+    const double d3 = delta * delta * delta, d5 = d3 * delta * delta, d7 = d5 * delta * delta;
+    const double K2 = oracle_F(2, rho) / d3, K3 = oracle_F(3, rho) / d3, K4 = oracle_F(4, rho) / d5;
+    const double dK1 = -oracle_F(3, rho) / d3;      /* grad K1 = dK1 * D */
+    const double dK2 = -oracle_G(2, rho) / d5;
+    const double dK3 = -3.0 * oracle_F(4, rho) / d5;
+    const double dK4 = -oracle_G(4, rho) / d7;
+    const double wj = w[j];
+    const double dn = d[0] * nj[0] + d[1] * nj[1] + d[2] * nj[2];
+    const double ad = a[0] * d[0] + a[1] * d[1] + a[2] * d[2];
+    const double ld = lam[0] * d[0] + lam[1] * d[1] + lam[2] * d[2];
+    const double df = d[0] * fj[0] + d[1] * fj[1] + d[2] * fj[2];
+    const double lf = lam[0] * fj[0] + lam[1] * fj[1] + lam[2] * fj[2];
+    const double c_l = 1.0 / (4.0 * PI), c_s = -3.0 / (4.0 * PI), c_v = 1.0 / (8.0 * PI * mu);
+    const double dp = pt[j] - pt[i];
+    for (int c = 0; c < 3; ++c) {
+        double t = 0.0;
+        /* Laplace double layer and single layer (weighted by lam1_i) */
+        t += lam1[i] * c_l * wj * dp * (nj[c] * K2 + dn * dK2 * d[c]);
+        t += lam1[i] * (mu / K) * c_l * wj * v[j] * dK1 * d[c];
+        /* stresslet (lam2_i .) */
+        t += c_s * wj * (a[c] * dn * ld * K4 + nj[c] * ad * ld * K4 + lam[c] * ad * dn * K4 + ad * dn * ld * dK4 * d[c]);
+        /* Stokeslet */
+        t += c_v * wj * (lf * dK1 * d[c] + (lam[c] * df + fj[c] * ld) * K3 + ld * df * dK3 * d[c]);
+        g[c] = t;
+    }
+}
+
+void oracle_coupled_xgrad(int64_t n, const double* x, const double* nrm, const double* w, double delta,
+                          double mu, double K, const double* pt, const double* v, const double* u,
+                          const double* f, const double* lam1, const double* lam2, double* grad)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t m = 0; m < n; ++m) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        double g[3];
+        for (int64_t j = 0; j < n; ++j) {          /* m as target */
+            pair_grad(n, x, nrm, w, delta, mu, K, pt, v, u, f, lam1, lam2, m, j, g);
+            for (int c = 0; c < 3; ++c) acc[c] -= g[c];
+        }
+        for (int64_t i = 0; i < n; ++i) {          /* m as source */
+            pair_grad(n, x, nrm, w, delta, mu, K, pt, v, u, f, lam1, lam2, i, m, g);
+            for (int c = 0; c < 3; ++c) acc[c] += g[c];
+        }
+        for (int c = 0; c < 3; ++c) grad[c * n + m] = acc[c];
+    }
+}
+
 int oracle_abi_version(void) { return 1; }
 
 /* threads the OpenMP loops above use */

@@ -44,7 +44,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol_gmres", ctypes.c_double), ("tol_ddm", ctypes.c_double), ("theta", ctypes.c_double),
                 ("maxit_gmres", ctypes.c_int), ("restart", ctypes.c_int), ("maxit_ddm", ctypes.c_int),
                 ("outer", ctypes.c_int), ("slip", ctypes.c_int), ("prec", ctypes.c_int),
-                ("tol_mixed", ctypes.c_double), ("refine_max", ctypes.c_int)]
+                ("tol_mixed", ctypes.c_double), ("refine_max", ctypes.c_int), ("mixed_mode", ctypes.c_int)]
 
 
 class KernelStat(ctypes.Structure):
@@ -95,6 +95,9 @@ def lib():
         L.ddm_solve.argtypes = [vp, ctypes.POINTER(Params), ctypes.POINTER(d), vp, vp, vp, ctypes.POINTER(d),
                                 ctypes.POINTER(Opts), ctypes.POINTER(Info), vp]
         L.ddm_solve.restype = i32
+        L.ddm_adjoint.argtypes = [vp, ctypes.POINTER(Params), ctypes.POINTER(d), vp, vp, vp, ctypes.POINTER(d), vp,
+                                  ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(Opts), ctypes.POINTER(Info), vp]
+        L.ddm_adjoint.restype = i32
         L.sdbie_last_error.argtypes = []
         L.sdbie_last_error.restype = ctypes.c_char_p
         L.sdbie_abi_version.argtypes = []
@@ -273,3 +276,23 @@ def ddm_solve(plan: Plan, mu, K, alpha, U, f_extra=None, opts=None):
     st = _check(lib().ddm_solve(plan.handle, ctypes.byref(prm), Uc, _ptr(f_extra), _ptr(p), _ptr(u), drag,
                                 ctypes.byref(o), ctypes.byref(info), _stream(plan.device)))
     return p, u, [drag[0], drag[1], drag[2]], info.as_dict(st)
+
+
+def ddm_adjoint(plan: Plan, mu, K, alpha, U, p, u, dJ_ddrag, f_extra=None, opts=None):
+    """Gradient of J = dJ_ddrag . drag at the converged ddm_solve outputs (p, u).
+
+    Returns (dJ_dx (3, N) device tensor, dJ_dlogK, dJ_dalpha, info dict).
+    """
+    p = _dev(p, (plan.n,), "p")
+    u = _dev(u, (3, plan.n), "u")
+    if f_extra is not None:
+        f_extra = _dev(f_extra, (3, plan.n), "f_extra")
+    gx = torch.empty((3, plan.n), dtype=torch.float64, device=plan.device)
+    Uc = (ctypes.c_double * 3)(*[float(v) for v in U])
+    ec = (ctypes.c_double * 3)(*[float(v) for v in dJ_ddrag])
+    gK, ga = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    prm, o, info = _params(mu, K, alpha), _opts(opts), Info()
+    st = _check(lib().ddm_adjoint(plan.handle, ctypes.byref(prm), Uc, _ptr(f_extra), _ptr(p), _ptr(u), ec, _ptr(gx),
+                                  ctypes.byref(gK), ctypes.byref(ga), ctypes.byref(o), ctypes.byref(info),
+                                  _stream(plan.device)))
+    return gx, gK.value, ga.value, info.as_dict(st)

@@ -139,6 +139,66 @@ __global__ void k_check_finite(const double* __restrict__ a, int64_t len, int* _
     if (i < len && !isfinite(a[i])) flag[0] = 1;
 }
 
+// ---- adjoint helpers ------------------------------------------------------
+// out = tn + lam * dl1 + w * (*sum) / area      (transposed completed Darcy operator)
+__global__ void k_adj_darcy(int64_t n, const double* __restrict__ tn, const double* __restrict__ lam,
+                            const double* __restrict__ dl1, const double* __restrict__ w,
+                            const double* __restrict__ sum, double inv_area, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = tn[i] + lam[i] * dl1[i] + w[i] * sum[0] * inv_area;
+}
+
+// out = lam + sum_c mneg_c lam_c + tns + w n (*flux)/area + beta w P_tau sv
+// (transposed completed Stokes operator with slip); mneg_c[a][i] = -(M_i)_{ac}
+__global__ void k_adj_stokes(int64_t n, const double* __restrict__ lam, const double* __restrict__ m0,
+                             const double* __restrict__ m1, const double* __restrict__ m2,
+                             const double* __restrict__ tns, const double* __restrict__ sv,
+                             const double* __restrict__ nrm, const double* __restrict__ w,
+                             const double* __restrict__ flux, double inv_area, double beta, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double l[3] = {lam[i], lam[n + i], lam[2 * n + i]};
+    const double nv[3] = {nrm[i], nrm[n + i], nrm[2 * n + i]};
+    double svn = 0.0;
+    if (sv) svn = sv[i] * nv[0] + sv[n + i] * nv[1] + sv[2 * n + i] * nv[2];
+    const double fl = flux[0] * inv_area;
+    for (int a = 0; a < 3; ++a) {
+        const int64_t k = a * n + i;
+        double v = l[a] + m0[k] * l[0] + m1[k] * l[1] + m2[k] * l[2] + tns[k] + w[i] * nv[a] * fl;
+        if (sv) v += beta * w[i] * (sv[k] - svn * nv[a]);
+        out[k] = v;
+    }
+}
+
+// out3 = scale * s n
+__global__ void k_scalar_normal(int64_t n, const double* __restrict__ s, double scale, const double* __restrict__ nrm,
+                                double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int c = 0; c < 3; ++c) out[c * n + i] = scale * s[i] * nrm[c * n + i];
+}
+
+// x += scale * (*d) * w
+__global__ void k_axpy_w(int64_t n, double* __restrict__ x, const double* __restrict__ w, const double* __restrict__ d,
+                         double scale) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] += scale * d[0] * w[i];
+}
+
+// gp = -w (e.n);  gu = beta w (e - (e.n) n)
+__global__ void k_adj_rhs(int64_t n, const double* __restrict__ nrm, const double* __restrict__ w, double e0, double e1,
+                          double e2, double beta, double* __restrict__ gp, double* __restrict__ gu) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double nx = nrm[i], ny = nrm[n + i], nz = nrm[2 * n + i];
+    const double en = e0 * nx + e1 * ny + e2 * nz;
+    gp[i] = -w[i] * en;
+    gu[i] = beta * w[i] * (e0 - en * nx);
+    gu[n + i] = beta * w[i] * (e1 - en * ny);
+    gu[2 * n + i] = beta * w[i] * (e2 - en * nz);
+}
+
 inline unsigned nblk(int64_t len) { return (unsigned)((len + 255) / 256); }
 
 }  // namespace
@@ -213,6 +273,36 @@ void dev_scatter(const Plan& P, const double* src, double* dst, int comps, hipSt
 
 void dev_check_finite(const double* a, int64_t len, int* flag, hipStream_t s) {
     hipLaunchKernelGGL(k_check_finite, dim3(nblk(len)), dim3(256), 0, s, a, len, flag);
+    SDBIE_LAUNCHED();
+}
+
+void dev_adj_darcy(const Plan& P, const double* tn, const double* lam, const double* dl1, const double* sum,
+                   double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_darcy, dim3(nblk(P.n)), dim3(256), 0, s, P.n, tn, lam, dl1, (const double*)P.w, sum,
+                       1.0 / P.area, out);
+    SDBIE_LAUNCHED();
+}
+
+void dev_adj_stokes(const Plan& P, const double* lam, const double* m0, const double* m1, const double* m2,
+                    const double* tns, const double* sv, const double* flux, double beta, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_stokes, dim3(nblk(P.n)), dim3(256), 0, s, P.n, lam, m0, m1, m2, tns, sv,
+                       (const double*)P.nrm, (const double*)P.w, flux, 1.0 / P.area, beta, out);
+    SDBIE_LAUNCHED();
+}
+
+void dev_scalar_normal(const Plan& P, const double* sv, double scale, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_scalar_normal, dim3(nblk(P.n)), dim3(256), 0, s, P.n, sv, scale, (const double*)P.nrm, out);
+    SDBIE_LAUNCHED();
+}
+
+void dev_axpy_w(const Plan& P, double* x, const double* d, double scale, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_w, dim3(nblk(P.n)), dim3(256), 0, s, P.n, x, (const double*)P.w, d, scale);
+    SDBIE_LAUNCHED();
+}
+
+void dev_adj_rhs(const Plan& P, const double e[3], double beta, double* gp, double* gu, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_rhs, dim3(nblk(P.n)), dim3(256), 0, s, P.n, (const double*)P.nrm, (const double*)P.w, e[0],
+                       e[1], e[2], beta, gp, gu);
     SDBIE_LAUNCHED();
 }
 

@@ -93,6 +93,7 @@ sdbie_opts checked_opts(const sdbie_opts* op, const Plan& P) {
     if (o.prec != SDBIE_FP64 && o.prec != SDBIE_MIXED) fail(SDBIE_ERR_ARG, "prec must be SDBIE_FP64 or SDBIE_MIXED");
     if (!(o.tol_mixed > 0.0 && o.tol_mixed < 1.0)) fail(SDBIE_ERR_ARG, "tol_mixed must lie in (0, 1)");
     if (o.refine_max < 1) fail(SDBIE_ERR_ARG, "refine_max must be >= 1");
+    if (o.mixed_mode != 0 && o.mixed_mode != 1) fail(SDBIE_ERR_ARG, "mixed_mode must be 0 or 1");
     return o;
 }
 
@@ -169,6 +170,7 @@ void sdbie_default_opts(sdbie_opts* o) {
     o->prec = SDBIE_FP64;
     o->tol_mixed = 1e-5;
     o->refine_max = 8;
+    o->mixed_mode = 0;
 }
 
 size_t sdbie_workspace_bytes(int64_t n, int max_restart) {
@@ -337,6 +339,34 @@ int ddm_solve(sdbie_plan plan, const sdbie_params* prm, const double U[3], const
         c.ddm(*prm, U, fx, ps, us, drag);
         dev_scatter(P, ps, p, 1, c.s);
         dev_scatter(P, us, u, 3, c.s);
+        SDBIE_HIP(hipStreamSynchronize(c.s));
+        c.finish();
+        if (info) *info = c.info;
+        return c.converged ? SDBIE_OK : SDBIE_NOT_CONVERGED;
+    });
+}
+
+int ddm_adjoint(sdbie_plan plan, const sdbie_params* prm, const double U[3], const double* f_extra, const double* p,
+                const double* u, const double dJ_ddrag[3], double* dJ_dx, double* dJ_dlogK, double* dJ_dalpha,
+                const sdbie_opts* opts, sdbie_info* info, void* stream) {
+    return guarded([&]() -> int {
+        Plan& P = plan_of(plan);
+        check_params(prm);
+        if (!U || !p || !u || !dJ_ddrag || !dJ_dx || !dJ_dlogK || !dJ_dalpha)
+            fail(SDBIE_ERR_ARG, "null argument");
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(U[k]) || !std::isfinite(dJ_ddrag[k])) fail(SDBIE_ERR_ARG, "non-finite U or dJ_ddrag");
+        const sdbie_opts o = checked_opts(opts, P);
+        Ctx c(P, stream_of(stream), o);
+        double* ps = P.vec(kVecP);
+        double* us = P.vec(kVecU);
+        double* fx = f_extra ? P.vec(kVecFx) : nullptr;
+        double* gs = P.vec(kVecSpare);
+        dev_gather(P, p, ps, 1, c.s);
+        dev_gather(P, u, us, 3, c.s);
+        if (fx) dev_gather(P, f_extra, fx, 3, c.s);
+        c.adjoint(*prm, U, fx, ps, us, dJ_ddrag, gs, dJ_dlogK, dJ_dalpha);
+        dev_scatter(P, gs, dJ_dx, 3, c.s);
         SDBIE_HIP(hipStreamSynchronize(c.s));
         c.finish();
         if (info) *info = c.info;

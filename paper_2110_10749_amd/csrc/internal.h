@@ -56,6 +56,23 @@ struct PassDesc {
     double* out = nullptr;            // sorted, or original order when scatter
     bool scatter = false;             // write out[perm[i]] instead of out[i]
     bool mixed = false;
+    // transposed sums (adjoint)
+    bool unit_src_weight = false;     // sources enter with weight 1 instead of w_j
+    bool target_weight = false;       // the pair sum is multiplied by the target's w_i
+    bool target_normal = false;       // double layer contracted with the target's normal (transposed DL)
+    const double* dl_target = nullptr;  // target density of the subtracted double layer (default dl_dens)
+};
+
+// Position-gradient pass of the adjoint: for every pair (i, j),
+//   g_ij = grad_D [lam1_i T1_ij + lam2_i . T2_ij],  D = x_i - x_j,
+//   T1_ij = c_l w_j (p_j - p_i)(D.n_j) K2 + (mu/K) c_l w_j v_j K1,
+//   T2_ij = c_s w_j ((u_j - u_i).D)(D.n_j) D K4 + c_v w_j [f_j K1 + D (D.f_j) K3],
+// with c_l = 1/(4 pi), c_s = -3/(4 pi), c_v = 1/(8 pi mu); the pass writes
+// out_m = -sum_j g_mj + sum_i g_im (derivative of -lam^T F w.r.t. x_m).
+struct GradDesc {
+    double mu, K;
+    const double *p, *v, *u, *f, *lam1, *lam2;  // sorted, stride n
+    double* out;                                // sorted [3][n]
 };
 
 struct Plan {
@@ -96,7 +113,7 @@ struct Plan {
     double* vec(int k) const { return vecs + (size_t)k * 3 * n; }
 };
 
-constexpr int kNumVec = 24;
+constexpr int kNumVec = 28;
 
 size_t workspace_bytes(int64_t n, int max_restart);
 void carve_workspace(Plan& P, void* ws);
@@ -104,6 +121,7 @@ void carve_workspace(Plan& P, void* ws);
 // kernels (pair_kernels.hip) ----------------------------------------------------
 void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t s);
 void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t s);
+void launch_grad_pass(const Plan& P, const GradDesc& g, hipStream_t s);
 int choose_splits(int64_t n);
 
 // kernel timing (profile.hip)
@@ -144,6 +162,15 @@ void dev_gather(const Plan& P, const double* src, double* dst, int comps, hipStr
 void dev_scatter(const Plan& P, const double* src, double* dst, int comps, hipStream_t s);
 // non-finite check: *flag (device int) set to 1 if any element is not finite
 void dev_check_finite(const double* a, int64_t len, int* flag, hipStream_t s);
+
+// adjoint helpers (see blas.hip)
+void dev_adj_darcy(const Plan& P, const double* tn, const double* lam, const double* dl1, const double* sum,
+                   double* out, hipStream_t s);
+void dev_adj_stokes(const Plan& P, const double* lam, const double* m0, const double* m1, const double* m2,
+                    const double* tns, const double* sv, const double* flux, double beta, double* out, hipStream_t s);
+void dev_scalar_normal(const Plan& P, const double* sv, double scale, double* out, hipStream_t s);
+void dev_axpy_w(const Plan& P, double* x, const double* d, double scale, hipStream_t s);
+void dev_adj_rhs(const Plan& P, const double e[3], double beta, double* gp, double* gu, hipStream_t s);
 
 // host-side helpers
 double host_read_scalar(const double* d, hipStream_t s);

@@ -33,6 +33,7 @@ namespace sdbie {
 namespace {
 
 constexpr double kTwoOverSqrtPi = 1.12837916709551257389615890312154517;  // 2/sqrt(pi)
+constexpr double kPiD = 3.14159265358979323846;
 
 __device__ __forceinline__ double rsq(double v) { return rsqrt(v); }
 __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
@@ -112,6 +113,11 @@ struct KArgs {
     double inv_delta;
     double rc2;         // (rho_cut * delta)^2
     double* partial;    // [2 nsplit][C][n]
+    int unit_w;         // sources enter with weight 1 (transposed single layers)
+    const double* dl_tgt;  // target density of the subtracted double layer (nullable: dl_dens)
+    // position-gradient pass
+    const double *g_p, *g_v, *g_u, *g_f, *g_l1, *g_l2;
+    double g_mu, g_K;
 };
 
 template <typename T> __device__ __forceinline__ T load_x(const KArgs& a, int c, int64_t j);
@@ -120,6 +126,10 @@ template <> __device__ __forceinline__ float load_x<float>(const KArgs& a, int c
 
 __device__ __forceinline__ double dens_at(const double* d, int64_t n, int c, int64_t j) {
     return j < n ? d[c * n + j] : 0.0;
+}
+
+__device__ __forceinline__ double src_weight(const KArgs& a, int64_t j) {
+    return a.unit_w ? (j < a.n ? 1.0 : 0.0) : a.w[j];
 }
 
 // --------------------------------------------------------------------------
@@ -148,7 +158,7 @@ struct LaplaceOp {
         s.x[t] = load_x<T>(a, 0, j);
         s.y[t] = load_x<T>(a, 1, j);
         s.z[t] = load_x<T>(a, 2, j);
-        const double wj = a.w[j];
+        const double wj = src_weight(a, j);
         if (DL) {
             const double c = a.c_dl * wj;
             s.nx[t] = T(c * a.nrm[j]);
@@ -203,9 +213,10 @@ struct StokesOp {
         yi = load_x<T>(a, 1, i);
         zi = load_x<T>(a, 2, i);
         if (DL && SUB) {
-            uix = T(dens_at(a.dl_dens, a.n, 0, i));
-            uiy = T(dens_at(a.dl_dens, a.n, 1, i));
-            uiz = T(dens_at(a.dl_dens, a.n, 2, i));
+            const double* tg = a.dl_tgt ? a.dl_tgt : a.dl_dens;
+            uix = T(dens_at(tg, a.n, 0, i));
+            uiy = T(dens_at(tg, a.n, 1, i));
+            uiz = T(dens_at(tg, a.n, 2, i));
         }
     }
     __device__ __forceinline__ void load(Smem& s, int t, int64_t j, const KArgs& a) const {
@@ -213,7 +224,7 @@ struct StokesOp {
         s.x[t] = load_x<T>(a, 0, j);
         s.y[t] = load_x<T>(a, 1, j);
         s.z[t] = load_x<T>(a, 2, j);
-        const double wj = a.w[j];
+        const double wj = src_weight(a, j);
         const double nx = a.nrm[j], ny = a.nrm[np + j], nz = a.nrm[2 * np + j];
         double ux = 0.0, uy = 0.0, uz = 0.0;
         if (DL || SLIP) {
@@ -279,6 +290,261 @@ struct StokesOp {
         az += (double)tz;
         tx = ty = tz = T(0);
     }
+    __device__ __forceinline__ void store(const KArgs& a, int slot, int64_t i) const {
+        double* o = a.partial + (int64_t)slot * 3 * a.n;
+        o[i] = ax;
+        o[a.n + i] = ay;
+        o[2 * a.n + i] = az;
+    }
+};
+
+// --------------------------------------------------------------------------
+// Transposed double layers (adjoint): the double-layer kernel contracted with
+// the TARGET's normal, sources weighted by c_dl (times w_j unless unit_w):
+//   Laplace:  out_i = n_i . sum_j c_dl w_j q_j D s2/r^3
+//   Stokes:   out_i = sum_j c_dl w_j (D.q_j)(D.n_i) D s4/r^5
+// --------------------------------------------------------------------------
+template <typename T>
+struct LaplaceTNOp {
+    static constexpr int C = 1;
+    struct Smem {
+        T x[kTile], y[kTile], z[kTile], q[kTile];
+    };
+    T xi, yi, zi, nxi, nyi, nzi;
+    double acc = 0.0;
+    T tacc = T(0);
+    __device__ __forceinline__ void init(const KArgs& a, int64_t i) {
+        xi = load_x<T>(a, 0, i);
+        yi = load_x<T>(a, 1, i);
+        zi = load_x<T>(a, 2, i);
+        nxi = T(a.nrm[i]);
+        nyi = T(a.nrm[a.npad + i]);
+        nzi = T(a.nrm[2 * a.npad + i]);
+    }
+    __device__ __forceinline__ void load(Smem& s, int t, int64_t j, const KArgs& a) const {
+        s.x[t] = load_x<T>(a, 0, j);
+        s.y[t] = load_x<T>(a, 1, j);
+        s.z[t] = load_x<T>(a, 2, j);
+        s.q[t] = T(a.c_dl * src_weight(a, j) * dens_at(a.dl_dens, a.n, 0, j));
+    }
+    template <bool NEAR>
+    __device__ __forceinline__ void pair(const Smem& s, int jj, T id, T id2, T rc2) {
+        const T dx = xi - s.x[jj], dy = yi - s.y[jj], dz = zi - s.z[jj];
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const T inv_r = rsq(r2);
+        T k1, k2 = inv_r * inv_r * inv_r, k3, k4;
+        if (NEAR && r2 < rc2) near_factors<T, false, true, false, false>(r2, inv_r, id, id2, k1, k2, k3, k4);
+        tacc += s.q[jj] * (dx * nxi + dy * nyi + dz * nzi) * k2;
+    }
+    __device__ __forceinline__ void flush() {
+        acc += (double)tacc;
+        tacc = T(0);
+    }
+    __device__ __forceinline__ void store(const KArgs& a, int slot, int64_t i) const {
+        a.partial[(int64_t)slot * a.n + i] = acc;
+    }
+};
+
+template <typename T>
+struct StokesTNOp {
+    static constexpr int C = 3;
+    struct Smem {
+        T x[kTile], y[kTile], z[kTile], qx[kTile], qy[kTile], qz[kTile];
+    };
+    T xi, yi, zi, nxi, nyi, nzi;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    T tx = T(0), ty = T(0), tz = T(0);
+    __device__ __forceinline__ void init(const KArgs& a, int64_t i) {
+        xi = load_x<T>(a, 0, i);
+        yi = load_x<T>(a, 1, i);
+        zi = load_x<T>(a, 2, i);
+        nxi = T(a.nrm[i]);
+        nyi = T(a.nrm[a.npad + i]);
+        nzi = T(a.nrm[2 * a.npad + i]);
+    }
+    __device__ __forceinline__ void load(Smem& s, int t, int64_t j, const KArgs& a) const {
+        s.x[t] = load_x<T>(a, 0, j);
+        s.y[t] = load_x<T>(a, 1, j);
+        s.z[t] = load_x<T>(a, 2, j);
+        const double c = a.c_dl * src_weight(a, j);
+        s.qx[t] = T(c * dens_at(a.dl_dens, a.n, 0, j));
+        s.qy[t] = T(c * dens_at(a.dl_dens, a.n, 1, j));
+        s.qz[t] = T(c * dens_at(a.dl_dens, a.n, 2, j));
+    }
+    template <bool NEAR>
+    __device__ __forceinline__ void pair(const Smem& s, int jj, T id, T id2, T rc2) {
+        const T dx = xi - s.x[jj], dy = yi - s.y[jj], dz = zi - s.z[jj];
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        const T inv_r = rsq(r2);
+        const T ir2 = inv_r * inv_r;
+        T k1, k2, k3, k4 = inv_r * ir2 * ir2;
+        if (NEAR && r2 < rc2) near_factors<T, false, false, false, true>(r2, inv_r, id, id2, k1, k2, k3, k4);
+        const T dq = dx * s.qx[jj] + dy * s.qy[jj] + dz * s.qz[jj];
+        const T c = dq * (dx * nxi + dy * nyi + dz * nzi) * k4;
+        tx += c * dx;
+        ty += c * dy;
+        tz += c * dz;
+    }
+    __device__ __forceinline__ void flush() {
+        ax += (double)tx;
+        ay += (double)ty;
+        az += (double)tz;
+        tx = ty = tz = T(0);
+    }
+    __device__ __forceinline__ void store(const KArgs& a, int slot, int64_t i) const {
+        double* o = a.partial + (int64_t)slot * 3 * a.n;
+        o[i] = ax;
+        o[a.n + i] = ay;
+        o[2 * a.n + i] = az;
+    }
+};
+
+// --------------------------------------------------------------------------
+// Position gradient of lam^T F (adjoint), double only.  See GradDesc.
+// G2/delta^5 = -(d/dr K2)/r and G4/delta^7 = -(d/dr K4)/r in the near field.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ void near_G(double r2, double inv_r, double id, double id2, double& g2, double& g4) {
+    const double x = r2 * id2;
+    const double id5 = id * id2 * id2;
+    if (x < Consts<double>::rho_s2) {
+        g2 = horner(kG2_F64, x) * id5;
+        g4 = horner(kG4_F64, x) * id5 * id2;
+    } else {
+        const double rho = r2 * inv_r * id;
+        const double ef = erf(rho);
+        const double E = exp(-x);
+        const double cE = kTwoOverSqrtPi * rho * E;
+        const double ir2 = inv_r * inv_r;
+        const double s2 = ef + cE * (1.0 / 3.0) * (2.0 * x - 3.0);
+        const double s4 = ef - cE * (1.0 / 9.0) * (((8.0 * x - 36.0) * x + 6.0) * x + 9.0);
+        const double ir5 = ir2 * ir2 * inv_r;
+        g2 = 3.0 * s2 * ir5 - kTwoOverSqrtPi * E * (4.0 - 4.0 * x / 3.0) * ir2 * id * id2;
+        g4 = 5.0 * s4 * ir5 * ir2 - (16.0 * kTwoOverSqrtPi / 9.0) * ((x - 8.0) * x + 12.0) * E * ir2 * id5;
+    }
+}
+
+struct GTgt { double x, y, z, p, ux, uy, uz, l1, lx, ly, lz; };
+struct GSrc { double x, y, z, nx, ny, nz, w, p, v, ux, uy, uz, fx, fy, fz; };
+
+__device__ __forceinline__ GTgt load_gtgt(const KArgs& a, int64_t i) {
+    GTgt t;
+    t.x = a.x[i];
+    t.y = a.x[a.npad + i];
+    t.z = a.x[2 * a.npad + i];
+    t.p = dens_at(a.g_p, a.n, 0, i);
+    t.ux = dens_at(a.g_u, a.n, 0, i);
+    t.uy = dens_at(a.g_u, a.n, 1, i);
+    t.uz = dens_at(a.g_u, a.n, 2, i);
+    t.l1 = dens_at(a.g_l1, a.n, 0, i);
+    t.lx = dens_at(a.g_l2, a.n, 0, i);
+    t.ly = dens_at(a.g_l2, a.n, 1, i);
+    t.lz = dens_at(a.g_l2, a.n, 2, i);
+    return t;
+}
+
+__device__ __forceinline__ GSrc load_gsrc(const KArgs& a, int64_t j) {
+    GSrc s;
+    s.x = a.x[j];
+    s.y = a.x[a.npad + j];
+    s.z = a.x[2 * a.npad + j];
+    s.nx = a.nrm[j];
+    s.ny = a.nrm[a.npad + j];
+    s.nz = a.nrm[2 * a.npad + j];
+    s.w = a.w[j];
+    s.p = dens_at(a.g_p, a.n, 0, j);
+    s.v = dens_at(a.g_v, a.n, 0, j);
+    s.ux = dens_at(a.g_u, a.n, 0, j);
+    s.uy = dens_at(a.g_u, a.n, 1, j);
+    s.uz = dens_at(a.g_u, a.n, 2, j);
+    s.fx = dens_at(a.g_f, a.n, 0, j);
+    s.fy = dens_at(a.g_f, a.n, 1, j);
+    s.fz = dens_at(a.g_f, a.n, 2, j);
+    return s;
+}
+
+template <bool NEAR>
+__device__ __forceinline__ void grad_pair(const GTgt& t, const GSrc& s, const KArgs& a, double id, double id2,
+                                          double rc2, double& gx, double& gy, double& gz) {
+    const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double inv_r = rsqrt(r2);
+    const double ir2 = inv_r * inv_r;
+    double k1, k2 = inv_r * ir2, k3 = k2, k4 = k2 * ir2;
+    double g2 = 3.0 * k4, g4 = 5.0 * k4 * ir2;
+    if (NEAR && r2 < rc2) {
+        near_factors<double, false, true, true, true>(r2, inv_r, id, id2, k1, k2, k3, k4);
+        near_G(r2, inv_r, id, id2, g2, g4);
+    }
+    // grad_D K1 = -K3 D, grad_D K2 = -g2 D, grad_D K3 = -3 K4 D, grad_D K4 = -g4 D
+    const double cl = 1.0 / (4.0 * kPiD), cs = -3.0 / (4.0 * kPiD), cv = 1.0 / (8.0 * kPiD * a.g_mu);
+    const double dn = dx * s.nx + dy * s.ny + dz * s.nz;
+    const double axv = s.ux - t.ux, ayv = s.uy - t.uy, azv = s.uz - t.uz;
+    const double ad = axv * dx + ayv * dy + azv * dz;
+    const double ld = t.lx * dx + t.ly * dy + t.lz * dz;
+    const double df = dx * s.fx + dy * s.fy + dz * s.fz;
+    const double lf = t.lx * s.fx + t.ly * s.fy + t.lz * s.fz;
+    const double w = s.w;
+    // coefficient of D (radial part) and of the vectors n_j, a, lam, f_j
+    const double cD = t.l1 * cl * w * (s.p - t.p) * dn * (-g2) + t.l1 * (a.g_mu / a.g_K) * cl * w * s.v * (-k3) +
+                      cs * w * ad * dn * ld * (-g4) + cv * w * (lf * (-k3) + ld * df * (-3.0 * k4));
+    const double cN = t.l1 * cl * w * (s.p - t.p) * k2 + cs * w * ad * ld * k4;
+    const double cA = cs * w * dn * ld * k4;
+    const double cL = cs * w * ad * dn * k4 + cv * w * df * k3;
+    const double cF = cv * w * ld * k3;
+    gx += cD * dx + cN * s.nx + cA * axv + cL * t.lx + cF * s.fx;
+    gy += cD * dy + cN * s.ny + cA * ayv + cL * t.ly + cF * s.fy;
+    gz += cD * dz + cN * s.nz + cA * azv + cL * t.lz + cF * s.fz;
+}
+
+// SWAP = false: the lane is the target i and the tile holds sources j;
+// SWAP = true: the lane is the source j and the tile holds targets i.
+template <bool SWAP>
+struct GradOp {
+    static constexpr int C = 3;
+    struct Smem {
+        double f[SWAP ? 11 : 15][kTile];
+    };
+    GTgt t;
+    GSrc s;
+    double ax = 0.0, ay = 0.0, az = 0.0;
+    const KArgs* ap;
+    __device__ __forceinline__ void init(const KArgs& a, int64_t i) {
+        ap = &a;
+        if (SWAP) s = load_gsrc(a, i);
+        else t = load_gtgt(a, i);
+    }
+    __device__ __forceinline__ void load(Smem& sm, int k, int64_t j, const KArgs& a) const {
+        if (SWAP) {
+            const GTgt q = load_gtgt(a, j);
+            const double v[11] = {q.x, q.y, q.z, q.p, q.ux, q.uy, q.uz, q.l1, q.lx, q.ly, q.lz};
+#pragma unroll
+            for (int f = 0; f < 11; ++f) sm.f[f][k] = v[f];
+        } else {
+            const GSrc q = load_gsrc(a, j);
+            const double v[15] = {q.x, q.y, q.z, q.nx, q.ny, q.nz, q.w, q.p, q.v, q.ux, q.uy, q.uz, q.fx, q.fy, q.fz};
+#pragma unroll
+            for (int f = 0; f < 15; ++f) sm.f[f][k] = v[f];
+        }
+    }
+    template <bool NEAR>
+    __device__ __forceinline__ void pair(const Smem& sm, int jj, double id, double id2, double rc2) {
+        if (SWAP) {
+            GTgt q;
+            q.x = sm.f[0][jj]; q.y = sm.f[1][jj]; q.z = sm.f[2][jj]; q.p = sm.f[3][jj];
+            q.ux = sm.f[4][jj]; q.uy = sm.f[5][jj]; q.uz = sm.f[6][jj]; q.l1 = sm.f[7][jj];
+            q.lx = sm.f[8][jj]; q.ly = sm.f[9][jj]; q.lz = sm.f[10][jj];
+            grad_pair<NEAR>(q, s, *ap, id, id2, rc2, ax, ay, az);
+        } else {
+            GSrc q;
+            q.x = sm.f[0][jj]; q.y = sm.f[1][jj]; q.z = sm.f[2][jj];
+            q.nx = sm.f[3][jj]; q.ny = sm.f[4][jj]; q.nz = sm.f[5][jj]; q.w = sm.f[6][jj];
+            q.p = sm.f[7][jj]; q.v = sm.f[8][jj];
+            q.ux = sm.f[9][jj]; q.uy = sm.f[10][jj]; q.uz = sm.f[11][jj];
+            q.fx = sm.f[12][jj]; q.fy = sm.f[13][jj]; q.fz = sm.f[14][jj];
+            grad_pair<NEAR>(t, q, *ap, id, id2, rc2, ax, ay, az);
+        }
+    }
+    __device__ __forceinline__ void flush() {}
     __device__ __forceinline__ void store(const KArgs& a, int slot, int64_t i) const {
         double* o = a.partial + (int64_t)slot * 3 * a.n;
         o[i] = ax;
@@ -353,6 +619,7 @@ __global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
 // out_i = sum_s partial[s][c][i] + base_scale*base + comp_scale*(*comp)*vecfac + add[c]
 template <int C>
 __global__ void epilogue(int64_t n, int nslots, const double* __restrict__ partial,
+                         const double* __restrict__ tw,
                          const double* __restrict__ base, double base_scale,
                          const double* __restrict__ comp, double comp_scale,
                          const double* __restrict__ nrm, double add0, double add1, double add2,
@@ -365,6 +632,7 @@ __global__ void epilogue(int64_t n, int nslots, const double* __restrict__ parti
     for (int c = 0; c < C; ++c) {
         double v = 0.0;
         for (int s = 0; s < nslots; ++s) v += partial[((int64_t)s * C + c) * n + i];
+        if (tw) v *= tw[i];
         if (base) v += base_scale * base[c * n + i];
         if (comp) v += cs * (C == 3 ? nrm[c * n + i] : 1.0);
         v += (c == 0 ? add0 : (c == 1 ? add1 : add2));
@@ -392,6 +660,10 @@ KArgs make_args(const Plan& P, const PassDesc& d, int nsplit, double cut) {
     a.inv_delta = 1.0 / P.delta;
     a.rc2 = (cut * P.delta) * (cut * P.delta);
     a.partial = P.partial;
+    a.unit_w = d.unit_src_weight ? 1 : 0;
+    a.dl_tgt = d.dl_target;
+    a.g_p = a.g_v = a.g_u = a.g_f = a.g_l1 = a.g_l2 = nullptr;
+    a.g_mu = a.g_K = 1.0;
     return a;
 }
 
@@ -421,7 +693,12 @@ void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
     const double cut = d.mixed ? (double)SDBIE_RHO_CUT_STOKES_F32 : SDBIE_RHO_CUT_STOKES_F64;
     const KArgs a = make_args(P, d, S, cut);
     const int code = (d.dl ? 1 : 0) | (d.sl ? 2 : 0) | (d.sub ? 4 : 0);
-    {
+    if (d.target_normal) {
+        if (!d.dl || d.sl || d.sub) throw Error(SDBIE_ERR_ARG, "transposed Laplace pass takes a double layer only");
+        ProfScope prof(prof_variant(0, d.mixed, 16 | 1), (double)P.n * (double)P.n, st);
+        if (d.mixed) launch_pair_kernels<LaplaceTNOp<float>, float>(a, st);
+        else launch_pair_kernels<LaplaceTNOp<double>, double>(a, st);
+    } else {
         ProfScope prof(prof_variant(0, d.mixed, d.sl && !d.dl ? 2 : code), (double)P.n * (double)P.n, st);
 #define SDBIE_LAP(T, DL, SL, SUB) launch_pair_kernels<LaplaceOp<T, DL, SL, SUB>, T>(a, st)
         if (!d.mixed) {
@@ -447,7 +724,8 @@ void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
     }
     const double* add = d.add_const;
     hipLaunchKernelGGL((epilogue<1>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P.n, 2 * S,
-                       (const double*)P.partial, d.base, d.base_scale, d.comp, d.comp_scale,
+                       (const double*)P.partial, d.target_weight ? (const double*)P.w : nullptr, d.base,
+                       d.base_scale, d.comp, d.comp_scale,
                        (const double*)P.nrm, add ? add[0] : 0.0, 0.0, 0.0, d.out,
                        d.scatter ? (const int32_t*)P.perm : nullptr);
     SDBIE_LAUNCHED();
@@ -462,7 +740,12 @@ void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
     const KArgs a = make_args(P, d, S, cut);
     const bool slip = d.sl && d.slip_beta != 0.0 && d.sl_dens == nullptr;
     const int code = (d.dl ? 1 : 0) | (d.sl ? 2 : 0) | (d.sub ? 4 : 0) | (slip ? 8 : 0);
-    {
+    if (d.target_normal) {
+        if (!d.dl || d.sl || d.sub) throw Error(SDBIE_ERR_ARG, "transposed Stokes pass takes a double layer only");
+        ProfScope prof(prof_variant(1, d.mixed, 16 | 1), (double)P.n * (double)P.n, st);
+        if (d.mixed) launch_pair_kernels<StokesTNOp<float>, float>(a, st);
+        else launch_pair_kernels<StokesTNOp<double>, double>(a, st);
+    } else {
         ProfScope prof(prof_variant(1, d.mixed, code), (double)P.n * (double)P.n, st);
 #define SDBIE_STO(T, DL, SL, SUB, SLIP) launch_pair_kernels<StokesOp<T, DL, SL, SUB, SLIP>, T>(a, st)
         if (!d.mixed) {
@@ -488,13 +771,47 @@ void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
     }
     const double* add = d.add_const;
     hipLaunchKernelGGL((epilogue<3>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P.n, 2 * S,
-                       (const double*)P.partial, d.base, d.base_scale, d.comp, d.comp_scale,
+                       (const double*)P.partial, d.target_weight ? (const double*)P.w : nullptr, d.base,
+                       d.base_scale, d.comp, d.comp_scale,
                        (const double*)P.nrm, add ? add[0] : 0.0, add ? add[1] : 0.0, add ? add[2] : 0.0,
                        d.out, d.scatter ? (const int32_t*)P.perm : nullptr);
     SDBIE_LAUNCHED();
     Plan& Pm = const_cast<Plan&>(P);
     (d.mixed ? Pm.applies_mixed : Pm.applies_fp64) += 1;
     Pm.pairs += (double)P.n * (double)P.n;
+}
+
+void launch_grad_pass(const Plan& P, const GradDesc& g, hipStream_t st) {
+    const int S = choose_splits(P.n);
+    PassDesc d;
+    KArgs a = make_args(P, d, S, SDBIE_RHO_CUT_STOKES_F64);
+    a.g_p = g.p;
+    a.g_v = g.v;
+    a.g_u = g.u;
+    a.g_f = g.f;
+    a.g_l1 = g.lam1;
+    a.g_l2 = g.lam2;
+    a.g_mu = g.mu;
+    a.g_K = g.K;
+    const unsigned eb = (unsigned)((P.n + 255) / 256);
+    {
+        ProfScope prof(prof_variant(2, false, 0), 2.0 * (double)P.n * (double)P.n, st);
+        // node as target: A_m = sum_j g_mj
+        launch_pair_kernels<GradOp<false>, double>(a, st);
+        hipLaunchKernelGGL((epilogue<3>), dim3(eb), dim3(256), 0, st, P.n, 2 * S, (const double*)P.partial,
+                           (const double*)nullptr, (const double*)nullptr, 0.0, (const double*)nullptr, 0.0,
+                           (const double*)P.nrm, 0.0, 0.0, 0.0, g.out, (const int32_t*)nullptr);
+        SDBIE_LAUNCHED();
+        // node as source: out = sum_i g_im - A_m
+        launch_pair_kernels<GradOp<true>, double>(a, st);
+    }
+    hipLaunchKernelGGL((epilogue<3>), dim3(eb), dim3(256), 0, st, P.n, 2 * S, (const double*)P.partial,
+                       (const double*)nullptr, (const double*)g.out, -1.0, (const double*)nullptr, 0.0,
+                       (const double*)P.nrm, 0.0, 0.0, 0.0, g.out, (const int32_t*)nullptr);
+    SDBIE_LAUNCHED();
+    Plan& Pm = const_cast<Plan&>(P);
+    Pm.applies_fp64 += 2;
+    Pm.pairs += 2.0 * (double)P.n * (double)P.n;
 }
 
 }  // namespace sdbie

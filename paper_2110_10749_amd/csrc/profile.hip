@@ -33,7 +33,9 @@ int prof_variant(int family, bool mixed, int code) { return family * 64 + (mixed
 
 std::string prof_name(int v) {
     const int family = v / 64, mixed = (v / 32) & 1, code = v & 31;
+    if (family == 2) return "position_gradient<f64>";
     std::string s = family == 0 ? "laplace_pairs<" : "stokes_pairs<";
+    if (code & 16) s = family == 0 ? "laplace_pairs_T<" : "stokes_pairs_T<";
     s += mixed ? "f32" : "f64";
     if (code & 1) s += ",DL";
     if (code & 2) s += ",SL";
@@ -45,6 +47,8 @@ std::string prof_name(int v) {
 double flops_per_pair(int v) {
     const int family = v / 64, code = v & 31;
     const bool dl = code & 1, sl = code & 2, sub = code & 4;
+    if (family == 2) return 0.0;  // not counted
+    if (code & 16) return family == 0 ? 9.0 + 2 + 5 + 3 : 9.0 + 2 + 5 + 5 + 2 + 6;
     // common: D (3), r^2 (1 mul + 2 fma = 5), rsqrt (1)
     double f = 9.0;
     if (family == 0) {

@@ -32,6 +32,9 @@ enum : int {
     kVecCoupledU,     // mixed coupled refinement: velocity iterate
     kVecCoupledR1,    // mixed coupled refinement: Darcy residual
     kVecCoupledR2,    // mixed coupled refinement: Stokes residual
+    kVecCoupledDP,    // mixed coupled refinement: pressure correction
+    kVecCoupledDU,    // mixed coupled refinement: velocity correction
+    kVecCoupledV,     // mixed coupled refinement: u.n / projected pressure
     kVecSpare,
 };
 static_assert(kVecSpare < kNumVec, "work-vector slots exceed the workspace");
@@ -68,6 +71,10 @@ struct Ctx {
     sdbie_info info;
     bool converged = true;
     GmresWS inner, outer;
+    // correction mode of the coupled refinement: every pass in float pairs,
+    // local solves by plain GMRES to tol_corr
+    bool corr = false;
+    double tol_corr = 0.0;
 
     Ctx(Plan& plan, hipStream_t st, const sdbie_opts& opts);
     void finish();
@@ -86,10 +93,19 @@ struct Ctx {
     void solve(const std::function<void(const double*, double*, bool)>& op, const double* b, double* x, int64_t L,
                bool x_nonzero, double* rbuf, double* cbuf);
 
-    void darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonzero, const double* extra_rhs);
+    void darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonzero, const double* extra_rhs,
+               bool remove_mean = true);
     void stokes(const sdbie_params& prm, const double U[3], const double* p, const double* fx, double* u,
                 bool u_nonzero, const double* extra_rhs);
     void ddm(const sdbie_params& prm, const double U[3], const double* fx, double* p, double* u, double drag[3]);
+    void ddm_outer(const sdbie_params& prm, const double U[3], const double* fx, const double* r1, const double* r2,
+                   double* p, double* u, bool remove_mean, double tol);
+    void coupled_residual(const sdbie_params& prm, const double U[3], const double* fx, const double* pt,
+                          const double* u, double* r1, double* r2);
+    void project_mean(const double* p, double* out);
+    void ddm_refined(const sdbie_params& prm, const double U[3], const double* fx, double* p, double* u);
+    void adjoint(const sdbie_params& prm, const double U[3], const double* fx, const double* p, const double* u,
+                 const double e[3], double* grad, double* dlogK, double* dalpha);
     void compute_drag(const sdbie_params& prm, const double* p, const double* u, const double* fx, double drag[3]);
 };
 

@@ -11,6 +11,8 @@
 // Mixed precision: the solve is wrapped in iterative refinement
 //   r = b - A64 x  (double pairs),  A32 c = r by GMRES (float pairs), x += c.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -20,6 +22,15 @@ namespace sdbie {
 
 namespace {
 constexpr double kPi = 3.14159265358979323846;
+
+// SDBIE_DEBUG=1 prints solver progress to stderr
+int debug_level() {
+    static const int lvl = [] {
+        const char* e = std::getenv("SDBIE_DEBUG");
+        return e ? std::atoi(e) : 0;
+    }();
+    return lvl;
+}
 }
 
 // ------------------------------------------------------------------------------
@@ -188,6 +199,9 @@ GmresOut Ctx::gmres(const GmresWS& ws, const std::function<void(const double*, d
     }
     res.conv = res.relres <= tol;
     SDBIE_HIP(hipStreamSynchronize(s));
+    if (debug_level() > 1)
+        std::fprintf(stderr, "[sdbie] gmres L=%lld iters=%d relres=%.3e tol=%.1e\n", (long long)L, res.iters,
+                     res.relres, tol);
     return res;
 }
 
@@ -195,6 +209,13 @@ GmresOut Ctx::gmres(const GmresWS& ws, const std::function<void(const double*, d
 // refinement (double residual, float-pair correction solves).
 void Ctx::solve(const std::function<void(const double*, double*, bool)>& op, const double* b, double* x,
                 int64_t L, bool x_nonzero, double* rbuf, double* cbuf) {
+    if (corr) {
+        const bool m32 = debug_level() < 10;  // SDBIE_DEBUG >= 10: double-pair corrections (diagnostics)
+        GmresOut g = gmres(inner, [&](const double* in, double* out) { op(in, out, m32); }, b, x, L, x_nonzero,
+                           tol_corr, o.restart, o.maxit_gmres);
+        info.gmres_iters += g.iters;
+        return;
+    }
     const bool mixed = o.prec == SDBIE_MIXED;
     if (!mixed) {
         GmresOut g = gmres(inner, [&](const double* in, double* out) { op(in, out, false); }, b, x, L, x_nonzero,
@@ -213,7 +234,18 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op, con
     bool have_x = x_nonzero;
     int step = 0;
     double rel = 1.0;
+    double predicted = -1.0;  // residual bound after an unverified correction
     for (;; ++step) {
+        if (predicted >= 0.0) {
+            // the last correction c solved A32 c = r to tol_c; the new residual
+            // r - A64 c = (r - A32 c) + (A32 - A64) c is bounded by
+            // rel * (tol_c + ||A32 - A64|| ||A^-1||) with the float-pair
+            // operator error ~3e-7 and ||A^-1|| ~ 10 for these second-kind
+            // operators; with a factor 2 of margin, accept it without a
+            // double-pair pass
+            rel = predicted;
+            break;
+        }
         if (have_x) {
             op(x, rbuf, false);
             dev_axpby(1.0, b, -1.0, rbuf, rbuf, L, s);
@@ -222,9 +254,8 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op, con
         }
         rel = norm(rbuf, L) / bnorm;
         if (rel <= o.tol_gmres || step >= o.refine_max) break;
-        const double tol_c = std::max(o.tol_mixed, 0.5 * o.tol_gmres / rel);
         GmresOut g = gmres(inner, [&](const double* in, double* out) { op(in, out, true); }, rbuf, cbuf, L, false,
-                           tol_c, o.restart, o.maxit_gmres);
+                           o.tol_mixed, o.restart, o.maxit_gmres);
         info.gmres_iters += g.iters;
         if (have_x) {
             dev_axpby(1.0, x, 1.0, cbuf, x, L, s);
@@ -232,6 +263,8 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op, con
             copy(cbuf, x, L);
             have_x = true;
         }
+        const double bound = 2.0 * rel * (g.relres + 5e-6);
+        if (g.conv && bound <= o.tol_gmres) predicted = bound;
     }
     info.refine_steps += step;
     info.relres = rel;
@@ -241,17 +274,19 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op, con
 // ------------------------------------------------------------------------------
 // local problems
 // ------------------------------------------------------------------------------
-void Ctx::darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonzero, const double* extra_rhs) {
+void Ctx::darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonzero, const double* extra_rhs,
+                bool remove_mean) {
     const int64_t n = P.n;
     double* b = P.vec(kVecDarcyB);
     // b = -S_L[g], g = dp/dn = -(mu/K) v   =>  b = (mu/K) S_L[v]
-    single_layer_laplace(v, prm.mu / prm.K, b, false);
+    single_layer_laplace(v, prm.mu / prm.K, b, corr && debug_level() < 10);
     if (extra_rhs) dev_axpby(1.0, b, 1.0, extra_rhs, b, n, s);
     solve([&](const double* in, double* out, bool mx) { op_darcy(in, out, mx); }, b, p, n, p_nonzero,
           P.vec(kVecRefR), P.vec(kVecRefC));
-    // remove the weighted mean
-    dev_dot(P, P.w, p, n, P.scal + kScalMean, s);
-    dev_add_scaled_scalar(p, P.scal + kScalMean, -1.0 / P.area, n, s);
+    if (remove_mean) {
+        dev_dot(P, P.w, p, n, P.scal + kScalMean, s);
+        dev_add_scaled_scalar(p, P.scal + kScalMean, -1.0 / P.area, n, s);
+    }
 }
 
 void Ctx::stokes(const sdbie_params& prm, const double U[3], const double* p, const double* fx, double* u,
@@ -263,7 +298,7 @@ void Ctx::stokes(const sdbie_params& prm, const double U[3], const double* p, co
     const bool lagged = o.slip == 1 && beta != 0.0;
     // traction without the implicit slip term (lagged slip uses the entry u)
     dev_traction(P, p, lagged ? u : nullptr, lagged ? beta : 0.0, fx, f, s);
-    single_layer_stokes(f, prm.mu, -1.0, U, rhs, false);
+    single_layer_stokes(f, prm.mu, -1.0, U, rhs, corr && debug_level() < 10);
     if (extra_rhs) dev_axpby(1.0, rhs, 1.0, extra_rhs, rhs, 3 * n, s);
     const double b_impl = lagged ? 0.0 : beta;
     solve([&](const double* in, double* out, bool mx) { op_stokes(in, out, prm.mu, b_impl, mx); }, rhs, u, 3 * n,
@@ -297,29 +332,370 @@ void Ctx::ddm(const sdbie_params& prm, const double U[3], const double* fx, doub
             if (info.ddm_res < o.tol_ddm) break;
         }
         if (!(info.ddm_res < o.tol_ddm)) converged = false;
+    } else if (o.prec == SDBIE_MIXED && o.mixed_mode == 1) {
+        ddm_refined(prm, U, fx, p, u);
     } else {
-        const double zero[3] = {0.0, 0.0, 0.0};
-        double* t0 = P.vec(kVecT0);
-        double* pl = P.vec(kVecPl);
-        double* ul = P.vec(kVecUl);
-        // t0 = T(0): Stokes with p = 0
-        dev_fill(0.0, pl, n, s);
-        stokes(prm, U, pl, fx, ul, false, nullptr);
-        dev_normal_component(P, ul, t0, s);
-        auto op = [&](const double* y, double* out) {
-            darcy(prm, y, pl, false, nullptr);
-            stokes(prm, zero, pl, nullptr, ul, false, nullptr);
-            dev_normal_component(P, ul, out, s);
-            dev_axpby(1.0, y, -1.0, out, out, n, s);
-        };
-        GmresOut g = gmres(outer, op, t0, v, n, false, o.tol_ddm, o.restart, o.maxit_ddm);
-        info.ddm_iters = g.iters;
-        info.ddm_res = g.relres;
-        if (!g.conv) converged = false;
-        darcy(prm, v, p, false, nullptr);
-        stokes(prm, U, p, fx, u, false, nullptr);
+        ddm_outer(prm, U, fx, nullptr, nullptr, p, u, true, o.tol_ddm);
     }
     compute_drag(prm, p, u, fx, drag);
+}
+
+// Interface GMRES: the D-N map T(v) = u(p(v)).n is affine in v; solve
+// (I - T_lin) v = T(0) and finish with one more Darcy and Stokes solve.
+// r1, r2 (nullable) are extra right-hand sides of the Darcy and Stokes
+// equations (used by the coupled refinement).
+void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx, const double* r1, const double* r2,
+                    double* p, double* u, bool remove_mean, double tol) {
+    const int64_t n = P.n;
+    const double zero[3] = {0.0, 0.0, 0.0};
+    double* v = P.vec(kVecV);
+    double* t0 = P.vec(kVecT0);
+    double* pl = P.vec(kVecPl);
+    double* ul = P.vec(kVecUl);
+    double* pp = P.vec(kVecCoupledV);
+    // t0 = T(0)
+    if (r1) {
+        dev_fill(0.0, v, n, s);
+        darcy(prm, v, pl, false, r1, remove_mean);
+    } else {
+        dev_fill(0.0, pl, n, s);
+    }
+    const double* pstk = pl;
+    if (!remove_mean && r1) {
+        project_mean(pl, pp);
+        pstk = pp;
+    }
+    stokes(prm, U, pstk, fx, ul, false, r2);
+    dev_normal_component(P, ul, t0, s);
+    auto op = [&](const double* y, double* out) {
+        darcy(prm, y, pl, false, nullptr, remove_mean);
+        const double* ps = pl;
+        if (!remove_mean) {
+            project_mean(pl, pp);
+            ps = pp;
+        }
+        stokes(prm, zero, ps, nullptr, ul, false, nullptr);
+        dev_normal_component(P, ul, out, s);
+        dev_axpby(1.0, y, -1.0, out, out, n, s);
+    };
+    GmresOut g = gmres(outer, op, t0, v, n, false, tol, o.restart, o.maxit_ddm);
+    info.ddm_iters += g.iters;
+    info.ddm_res = g.relres;
+    if (!g.conv && !corr) converged = false;
+    darcy(prm, v, p, false, r1, remove_mean);
+    const double* ps = p;
+    if (!remove_mean) {
+        project_mean(p, pp);
+        ps = pp;
+    }
+    stokes(prm, U, ps, fx, u, false, r2);
+}
+
+// out = p - (sum_j w_j p_j / |S|)
+void Ctx::project_mean(const double* p, double* out) {
+    copy(p, out, P.n);
+    dev_dot(P, P.w, p, P.n, P.scal + kScalMean, s);
+    dev_add_scaled_scalar(out, P.scal + kScalMean, -1.0 / P.area, P.n, s);
+}
+
+// Residual of the coupled system whose solution is the D-N fixed point.
+// Unknowns: pt (Darcy pressure before its weighted mean is removed) and u.
+//   r1 = -(Abar_D pt - (mu/K) S_L[u.n])
+//   r2 = U - (Abar_S u + V[-(Pi pt) n + beta P_tau u + f_extra])
+// Two fused double-pair passes (Laplace double + single layer, stresslet +
+// Stokeslet).
+void Ctx::coupled_residual(const sdbie_params& prm, const double U[3], const double* fx, const double* pt,
+                           const double* u, double* r1, double* r2) {
+    const int64_t n = P.n;
+    const double beta = prm.alpha * prm.mu / std::sqrt(prm.K);
+    double* vn = P.vec(kVecCoupledV);
+    dev_normal_component(P, u, vn, s);
+    dev_dot(P, P.w, pt, n, P.scal + kScalCompD, s);
+    PassDesc d;
+    d.dl = true;
+    d.sub = true;
+    d.c_dl = -1.0 / (4.0 * kPi);
+    d.dl_dens = pt;
+    d.sl = true;
+    d.c_sl = -(prm.mu / prm.K) / (4.0 * kPi);
+    d.sl_dens = vn;
+    d.comp = P.scal + kScalCompD;
+    d.comp_scale = -1.0 / P.area;
+    d.out = r1;
+    launch_laplace_pass(P, d, s);
+    // projected pressure and the traction
+    double* f = P.vec(kVecTraction);
+    project_mean(pt, vn);
+    dev_traction(P, vn, u, beta, fx, f, s);
+    dev_dot(P, P.wn, u, 3 * n, P.scal + kScalCompS, s);
+    PassDesc e;
+    e.dl = true;
+    e.sub = true;
+    e.c_dl = 3.0 / (4.0 * kPi);
+    e.dl_dens = u;
+    e.base = u;
+    e.base_scale = -1.0;
+    e.sl = true;
+    e.c_sl = -1.0 / (8.0 * kPi * prm.mu);
+    e.sl_dens = f;
+    e.comp = P.scal + kScalCompS;
+    e.comp_scale = -1.0 / P.area;
+    e.add_const = U;
+    e.out = r2;
+    launch_stokes_pass(P, e, s);
+}
+
+// Mixed-precision coupled solve: iterative refinement of the coupled system
+// with double-pair residuals; each correction is a D-N solve (interface
+// GMRES, local GMRES) with float-pair operators.  The local solves stop at
+// tol_mixed; the interface GMRES at tol_mixed * min(1, K / (mu R^2)) with R
+// the equivalent radius of the surface: the correction's Darcy equation sees
+// the interface iterate v instead of the final u.n, and the Darcy residual
+// it leaves behind is (mu/K) S_L[u.n - v], so the interface tolerance is
+// scaled by K/mu to keep the contraction per step near tol_mixed.  Stops
+// when ||r|| <= tol_ddm ||b|| (b: the right-hand side at u = p = 0).
+void Ctx::ddm_refined(const sdbie_params& prm, const double U[3], const double* fx, double* p, double* u) {
+    const int64_t n = P.n;
+    double* pt = P.vec(kVecCoupledP);
+    double* uu = P.vec(kVecCoupledU);
+    double* r1 = P.vec(kVecCoupledR1);
+    double* r2 = P.vec(kVecCoupledR2);
+    double* dp = P.vec(kVecCoupledDP);
+    double* du = P.vec(kVecCoupledDU);
+    dev_fill(0.0, pt, n, s);
+    dev_fill(0.0, uu, 3 * n, s);
+    dev_fill(0.0, r1, n, s);
+    if (fx) {
+        single_layer_stokes(fx, prm.mu, -1.0, U, r2, false);
+    } else {
+        for (int c = 0; c < 3; ++c) dev_fill(U[c], r2 + c * n, n, s);
+    }
+    const double bnorm = std::sqrt(dot(r2, r2, 3 * n));
+    const double target = o.tol_ddm;
+    double rel = 1.0;
+    int step = 0;
+    for (;; ++step) {
+        if (step > 0) coupled_residual(prm, U, fx, pt, uu, r1, r2);
+        rel = bnorm > 0.0 ? std::sqrt(dot(r1, r1, n) + dot(r2, r2, 3 * n)) / bnorm : 0.0;
+        if (debug_level() > 0)
+            std::fprintf(stderr, "[sdbie] coupled refinement step %d: ||r||/||b|| = %.3e (r1 %.3e, r2 %.3e)\n", step,
+                         rel, std::sqrt(dot(r1, r1, n)) / bnorm, std::sqrt(dot(r2, r2, 3 * n)) / bnorm);
+        if (rel <= target || step >= o.refine_max) break;
+        corr = true;
+        tol_corr = o.tol_mixed;
+        const double R2 = P.area / (4.0 * kPi);
+        const double tol_if = tol_corr * std::min(1.0, prm.K / (prm.mu * R2));
+        const double zero[3] = {0.0, 0.0, 0.0};
+        ddm_outer(prm, zero, nullptr, r1, r2, dp, du, false, tol_if);
+        corr = false;
+        dev_axpby(1.0, pt, 1.0, dp, pt, n, s);
+        dev_axpby(1.0, uu, 1.0, du, uu, 3 * n, s);
+    }
+    info.refine_steps += step;
+    info.relres = rel;
+    if (rel > target) converged = false;
+    project_mean(pt, p);
+    copy(uu, u, 3 * n);
+}
+
+// ------------------------------------------------------------------------------
+// Adjoint of the coupled solve (gradient of J = e . drag)
+// ------------------------------------------------------------------------------
+// Forward (the D-N fixed point, unknowns pt and u):
+//   F1 = Abar_D pt - (mu/K) S_L[N u] = 0,
+//   F2 = (Abar_S + beta V P_tau) u - V[Nhat Pi pt] + V[f_extra] - U = 0,
+//   J  = e . sum_j w_j f_j,  f = -(Pi pt) n + beta P_tau u + f_extra,
+// with N u = u.n, Nhat p = p n, Pi = I - 1 w^T/|S|.  The adjoint system
+//   Abar_D^T lam1 - Pi^T Nhat^T V^T lam2 = dJ/dpt = Pi^T (-w (e.n)),
+//   -(mu/K) N^T S_L^T lam1 + (Abar_S + beta V P_tau)^T lam2 = dJ/du = beta w P_tau e,
+// is solved by the transposed interface iteration on lam1 (GMRES on the affine
+// map lam1 -> Abar_D^-T [dJ/dpt + Pi^T Nhat^T V^T S^-T (dJ/du + (mu/K) N^T S_L^T lam1)]).
+// Transposed sums: S_L^T l = w (.) S~[l] and V^T l = w (.) V~[l] (unit source
+// weights, target weight); A_D^T l = -(1/4pi) w (.) n.sum l_s D K2 + l (.) D_L[1];
+// A_S^T l = l - M l + (3/4pi) w (.) sum (D.l_s)(D.n_t) D K4 with the stresslet
+// moment M_t = -(3/4pi) sum_s w_s (D.n_s) K4 D D^T.  Then
+//   dJ/dx    = -lam^T dF/dx   (position-gradient pass; normals and weights fixed)
+//   dJ/dlogK = -(beta/2) e.sum w P_tau u - lam1.(mu/K) S_L[u.n] + (beta/2) lam2.V[P_tau u]
+//   dJ/dalpha = (beta/alpha) [e.sum w P_tau u - lam2.V[P_tau u]]
+// p (= Pi pt) replaces pt throughout: every term sees pt only through
+// differences pt_j - pt_i or through Pi pt.
+void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, const double* p, const double* u,
+                  const double e[3], double* grad, double* dlogK, double* dalpha) {
+    (void)U;
+    const int64_t n = P.n;
+    const double mu = prm.mu, K = prm.K;
+    const double beta = prm.alpha * mu / std::sqrt(K);
+    double* lam1 = P.vec(kVecV);
+    double* dl1 = P.vec(kVecVn);
+    double* t0 = P.vec(kVecT0);
+    double* tD = P.vec(kVecPl);      // n-vector temporaries
+    double* tE = P.vec(kVecUl);      // 3n rhs of the transposed Stokes solve
+    double* tA = P.vec(kVecDarcyB);  // transposed Darcy operator temp
+    double* tB = P.vec(kVecStokesB); // transposed stresslet temp
+    double* tC = P.vec(kVecTraction);// transposed Stokeslet temp
+    double* x2 = P.vec(kVecIn);
+    double* tG = P.vec(kVecOut);
+    double* x1 = P.vec(kVecCoupledV);
+    double* m0 = P.vec(kVecCoupledP);
+    double* m1 = P.vec(kVecCoupledU);
+    double* m2 = P.vec(kVecCoupledR1);
+    double* gp = P.vec(kVecCoupledR2);
+    double* gu = P.vec(kVecCoupledDP);
+    double* lam2 = P.vec(kVecCoupledDU);
+    double* mneg[3] = {m0, m1, m2};
+
+    // diagonal terms: D_L[1] and -M e_c (subtracted stresslet with zero source density)
+    dev_fill(1.0, tD, n, s);
+    {
+        PassDesc d;
+        d.dl = true;
+        d.c_dl = -1.0 / (4.0 * kPi);
+        d.dl_dens = tD;
+        d.out = dl1;
+        launch_laplace_pass(P, d, s);
+    }
+    dev_fill(0.0, tE, 3 * n, s);
+    for (int c = 0; c < 3; ++c) {
+        dev_fill(0.0, tG, 3 * n, s);
+        dev_fill(1.0, tG + c * n, n, s);
+        PassDesc d;
+        d.dl = true;
+        d.sub = true;
+        d.c_dl = -3.0 / (4.0 * kPi);
+        d.dl_dens = tE;
+        d.dl_target = tG;
+        d.out = mneg[c];
+        launch_stokes_pass(P, d, s);
+    }
+    // transposed operators
+    auto opDT = [&](const double* l, double* out) {
+        PassDesc d;
+        d.dl = true;
+        d.target_normal = true;
+        d.unit_src_weight = true;
+        d.target_weight = true;
+        d.c_dl = -1.0 / (4.0 * kPi);
+        d.dl_dens = l;
+        d.out = tA;
+        launch_laplace_pass(P, d, s);
+        dev_dot(P, l, nullptr, n, P.scal + kScalCompD, s);
+        dev_adj_darcy(P, tA, l, dl1, P.scal + kScalCompD, out, s);
+    };
+    auto opST = [&](const double* l, double* out) {
+        PassDesc d;
+        d.dl = true;
+        d.target_normal = true;
+        d.unit_src_weight = true;
+        d.target_weight = true;
+        d.c_dl = 3.0 / (4.0 * kPi);
+        d.dl_dens = l;
+        d.out = tB;
+        launch_stokes_pass(P, d, s);
+        if (beta != 0.0) {
+            PassDesc e2;
+            e2.sl = true;
+            e2.unit_src_weight = true;
+            e2.c_sl = 1.0 / (8.0 * kPi * mu);
+            e2.sl_dens = l;
+            e2.out = tC;
+            launch_stokes_pass(P, e2, s);
+        }
+        dev_normal_component(P, l, tD, s);
+        dev_dot(P, tD, nullptr, n, P.scal + kScalCompS, s);
+        dev_adj_stokes(P, l, m0, m1, m2, tB, beta != 0.0 ? tC : nullptr, P.scal + kScalCompS, beta, out, s);
+    };
+    auto solve_T = [&](const std::function<void(const double*, double*)>& op, const double* b, double* x, int64_t L) {
+        GmresOut g = gmres(inner, op, b, x, L, false, o.tol_gmres, o.restart, o.maxit_gmres);
+        info.gmres_iters += g.iters;
+        info.relres = g.relres;
+        if (!g.conv) converged = false;
+    };
+    // transposed single layers: out = w (.) S~[l] (scaled) / w (.) V~[l]
+    auto SLT = [&](const double* l, double scale, double* out) {
+        PassDesc d;
+        d.sl = true;
+        d.unit_src_weight = true;
+        d.target_weight = true;
+        d.c_sl = -scale / (4.0 * kPi);
+        d.sl_dens = l;
+        d.out = out;
+        launch_laplace_pass(P, d, s);
+    };
+    auto VT = [&](const double* l, double* out) {
+        PassDesc d;
+        d.sl = true;
+        d.unit_src_weight = true;
+        d.target_weight = true;
+        d.c_sl = 1.0 / (8.0 * kPi * mu);
+        d.sl_dens = l;
+        d.out = out;
+        launch_stokes_pass(P, d, s);
+    };
+    // Pi^T g = g - w (sum g)/|S|   (in place)
+    auto PiT = [&](double* g) {
+        dev_dot(P, g, nullptr, n, P.scal + kScalMean, s);
+        dev_axpy_w(P, g, P.scal + kScalMean, -1.0 / P.area, s);
+    };
+    // y -> Abar_D^-T [base + Pi^T Nhat^T V^T S^-T (rhs3)],  rhs3 in tE
+    auto chain = [&](const double* base, double* out) {
+        solve_T(opST, tE, x2, 3 * n);   // x2 = S^-T rhs3
+        VT(x2, tG);                     // tG = V^T x2
+        dev_normal_component(P, tG, tD, s);
+        PiT(tD);
+        if (base) dev_axpby(1.0, tD, 1.0, base, tD, n, s);
+        solve_T(opDT, tD, out, n);
+    };
+
+    dev_adj_rhs(P, e, beta, gp, gu, s);
+    PiT(gp);
+    // t0 = T'(0)
+    copy(gu, tE, 3 * n);
+    chain(gp, t0);
+    auto opOuter = [&](const double* y, double* out) {
+        SLT(y, 1.0, tA);                          // S_L^T y
+        dev_scalar_normal(P, tA, mu / K, tE, s);  // (mu/K) N^T S_L^T y
+        chain(nullptr, x1);
+        dev_axpby(1.0, y, -1.0, x1, out, n, s);
+    };
+    GmresOut g = gmres(outer, opOuter, t0, lam1, n, false, o.tol_ddm, o.restart, o.maxit_ddm);
+    info.ddm_iters = g.iters;
+    info.ddm_res = g.relres;
+    if (!g.conv) converged = false;
+    // lam2 = S^-T (gu + (mu/K) N^T S_L^T lam1)
+    SLT(lam1, 1.0, tA);
+    dev_scalar_normal(P, tA, mu / K, tE, s);
+    dev_axpby(1.0, tE, 1.0, gu, tE, 3 * n, s);
+    solve_T(opST, tE, lam2, 3 * n);
+
+    // position gradient
+    double* v = P.vec(kVecRefR);
+    double* f = P.vec(kVecRefC);
+    dev_normal_component(P, u, v, s);
+    dev_traction(P, p, u, beta, fx, f, s);
+    GradDesc gd;
+    gd.mu = mu;
+    gd.K = K;
+    gd.p = p;
+    gd.v = v;
+    gd.u = u;
+    gd.f = f;
+    gd.lam1 = lam1;
+    gd.lam2 = lam2;
+    gd.out = grad;
+    launch_grad_pass(P, gd, s);
+
+    // parameter derivatives
+    double* tu = tC;
+    dev_traction(P, nullptr, u, 1.0, nullptr, tu, s);  // P_tau u
+    double ewtu = 0.0;
+    for (int c = 0; c < 3; ++c) ewtu += e[c] * dot(P.w, tu + c * n, n);
+    single_layer_laplace(v, 1.0, tA, false);             // S_L[u.n]
+    single_layer_stokes(tu, mu, 1.0, nullptr, tG, false); // V[P_tau u]
+    const double l1S = dot(lam1, tA, n);
+    const double l2V = dot(lam2, tG, 3 * n);
+    *dlogK = -(beta / 2.0) * ewtu - (mu / K) * l1S + (beta / 2.0) * l2V;
+    const double sa = mu / std::sqrt(K);
+    *dalpha = sa * (ewtu - l2V);
 }
 
 void Ctx::compute_drag(const sdbie_params& prm, const double* p, const double* u, const double* fx, double drag[3]) {

@@ -1,0 +1,111 @@
+"""GPU adjoint (gradient of drag) against the oracle and finite differences.
+
+* the oracle's dense adjoint (transposed monolithic solve + plain position
+  derivative loops, itself pinned to central differences on the CPU) on a
+  small ellipsoid: relative agreement 1e-8;
+* central finite differences of the GPU forward solve (step 1e-6 in the node
+  positions and 1e-5 in log K and alpha, tight solver tolerances) on a
+  perturbed sphere: relative agreement 1e-5 (FD noise ~ tol/step);
+* the torch.autograd.Function gives the same numbers as the direct call.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from workloads import exact, fields, surfaces
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = dict(prec="fp64", tol_gmres=1e-13, tol_ddm=1e-12)
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import paper_2110_10749_amd as sd
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return sd
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+@pytest.mark.parametrize("K,alpha,forced", [(1e-2, 1.0, False), (1.0, 0.3, True)])
+def test_adjoint_matches_oracle_dense_adjoint(sd, K, alpha, forced):
+    S = surfaces.ellipsoid(1.0 / 8, 1.0, 0.8, 0.6)
+    delta = 3.0 / 8
+    U = fields.unit_vector(5)
+    e = np.array([0.2, -0.4, 1.0])
+    fx = 0.2 * fields.smooth_vector(S.x, 9) if forced else None
+    geo = O.Geometry(S.x, S.n, S.w, delta)
+    prm = O.Params(1.0, K, alpha)
+    gx_o, gK_o, ga_o, (p_o, u_o, D_o) = O.coupled_dense_adjoint(geo, prm, U, e, fx)
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), delta)
+    fxd = dev(fx) if forced else None
+    p, u, D, info = sd.ddm_solve(plan, 1.0, K, alpha, U, fxd, opts=TIGHT)
+    assert info["converged"] and rel(D, D_o) < 1e-10
+    gx, gK, ga, ainfo = sd.ddm_adjoint(plan, 1.0, K, alpha, U, p, u, e, fxd, opts=TIGHT)
+    gx = gx.cpu().numpy()
+    print(ainfo, rel(gx, gx_o), gK, gK_o, ga, ga_o, flush=True)
+    assert ainfo["converged"]
+    assert rel(gx, gx_o) < 1e-8
+    assert abs(gK - gK_o) < 1e-8 * abs(gK_o)
+    assert abs(ga - ga_o) < 1e-8 * abs(ga_o)
+
+
+def test_adjoint_matches_central_differences(sd):
+    S = surfaces.perturbed_sphere(1.0 / 16, lmax=4, sigma=0.05, seed=4)
+    delta = 3.0 / 16
+    K, alpha = 1e-2, 1.0
+    U = fields.unit_vector(7)
+    e = fields.unit_vector(8)
+
+    def J(x, K=K, alpha=alpha):
+        plan = sd.Plan(dev(x), dev(S.n), dev(S.w), delta)
+        _, _, D, info = sd.ddm_solve(plan, 1.0, K, alpha, U, None, opts=TIGHT)
+        assert info["converged"]
+        return float(np.dot(e, D))
+
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), delta)
+    p, u, D, info = sd.ddm_solve(plan, 1.0, K, alpha, U, None, opts=TIGHT)
+    gx, gK, ga, ainfo = sd.ddm_adjoint(plan, 1.0, K, alpha, U, p, u, e, None, opts=TIGHT)
+    gx = gx.cpu().numpy()
+    h = 1e-5
+    fdK = (J(S.x, K=K * math.exp(h)) - J(S.x, K=K * math.exp(-h))) / (2 * h)
+    fda = (J(S.x, alpha=alpha + h) - J(S.x, alpha=alpha - h)) / (2 * h)
+    print("logK", gK, fdK, "alpha", ga, fda, flush=True)
+    assert abs(gK - fdK) < 1e-5 * abs(fdK)
+    assert abs(ga - fda) < 1e-5 * abs(fda)
+    h = 1e-6
+    for k in range(3):
+        V = fields.random_vector(S.N, 200 + k)
+        fd = (J(S.x + h * V) - J(S.x - h * V)) / (2 * h)
+        ad = float((gx * V).sum())
+        print("direction", k, ad, fd, flush=True)
+        assert abs(ad - fd) < 1e-5 * max(abs(fd), 1e-3)
+
+
+def test_autograd_function(sd):
+    S = surfaces.sphere(1.0 / 8)
+    x = dev(S.x).requires_grad_(True)
+    logK = torch.tensor(math.log(1e-2), dtype=torch.float64, device="cuda", requires_grad=True)
+    alpha = torch.tensor(1.0, dtype=torch.float64, device="cuda", requires_grad=True)
+    e = torch.tensor([0.0, 0.0, 1.0], dtype=torch.float64, device="cuda")
+    D = sd.drag(x, logK, alpha, dev(S.n), dev(S.w), 3.0 / 8, opts=TIGHT)
+    (D * e).sum().backward()
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / 8)
+    p, u, D2, _ = sd.ddm_solve(plan, 1.0, 1e-2, 1.0, [0, 0, 1], None, opts=TIGHT)
+    gx, gK, ga, _ = sd.ddm_adjoint(plan, 1.0, 1e-2, 1.0, [0, 0, 1], p, u, [0, 0, 1], None, opts=TIGHT)
+    assert torch.allclose(x.grad, gx, rtol=1e-12, atol=1e-14)
+    assert abs(logK.grad.item() - gK) < 1e-12 * abs(gK)
+    assert abs(alpha.grad.item() - ga) < 1e-12 * abs(ga)
+    # the drag itself is the closed-form one to discretisation accuracy
+    De = exact.bjs_drag(K=1e-2, beta=10.0)
+    assert abs(D[2].item() - De) / De < 2e-3

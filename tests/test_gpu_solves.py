@@ -169,3 +169,33 @@ def test_plans_are_independent_and_reusable(sd):
     _ = sd.laplace_layer_apply(b, "sl", dev(fields.random_scalar(S2.N, 2)))
     r1b = host(sd.laplace_layer_apply(a, "sl", q1))
     assert np.array_equal(r1, r1b)  # deterministic, bitwise
+
+
+@pytest.mark.parametrize("inv_h,K,alpha", [(32, 1.0, 0.1), (32, 1e-2, 1.0), (16, 1e-4, 10.0)])
+def test_mixed_matches_fp64_at_solver_tolerances(sd, inv_h, K, alpha):
+    # default tolerances (local 1e-10, interface 1e-8): the mixed solve (float
+    # pairs, double refinement) lands on the same drag as the FP64 path.
+    # beta = alpha mu / sqrt(K) spans 0.1 .. 1000; at large beta the implicit-slip
+    # Stokes operator behaves like I + beta (smoothing single layer) and needs a
+    # long Krylov space (restart 200)
+    S = surfaces.sphere(1.0 / inv_h)
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / inv_h, max_restart=200)
+    o = dict(restart=200, maxit_gmres=2000)
+    p64, u64, D64, i64 = sd.ddm_solve(plan, 1.0, K, alpha, E, None, opts=dict(prec="fp64", **o))
+    print("fp64", D64[2], i64, flush=True)
+    p32, u32, D32, i32 = sd.ddm_solve(plan, 1.0, K, alpha, E, None, opts=dict(prec="mixed", **o))
+    print("mixed", D32[2], i32, flush=True)
+    De = exact.bjs_drag(K=K, beta=alpha / math.sqrt(K))
+    assert i64["converged"] and i32["converged"]
+    assert abs(D32[2] - D64[2]) < 1e-8 * abs(D64[2])
+    assert rel(host(u32), host(u64)) < 1e-7
+    assert abs(D64[2] - De) / De < 2e-4
+
+
+def test_mixed_benchmark_mode_with_forcing(sd, s16):
+    S, geo, ops, plan = s16
+    fx = exact.jt_viscous_traction(S.x, E, K=1e-2)
+    p, u, D, info = sd.ddm_solve(plan, 1.0, 1e-2, 0.0, E, dev(fx), opts=dict(prec="mixed", **TIGHT))
+    pb, ub, Db = O.coupled_dense_solve(geo, O.Params(1.0, 1e-2, 0.0), E, fx)
+    assert info["converged"]
+    assert rel(host(p), pb) < 1e-9 and rel(host(u), ub) < 1e-9 and rel(D, Db) < 1e-10
