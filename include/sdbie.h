@@ -65,7 +65,9 @@ typedef enum { SDBIE_SL = 0, SDBIE_DL_RAW = 1, SDBIE_DL_SUB = 2 } sdbie_layer;
 /* Node set of a closed surface (section "Quadrature", eq. (Quadrature)):
  * points x, unit normals nrm pointing out of the porous body into the fluid,
  * quadrature weights w >= 0 (device memory, [3][n], [3][n], [n]), and the
- * regularisation width delta > 0 (the paper uses delta = 3h). */
+ * regularisation width delta > 0 (the paper uses delta = 3h).  Accepted
+ * range: |coordinates| <= 1e15 and 1e-15 <= delta <= 1e15 (every squared
+ * pair distance is then a normal number in float and double). */
 typedef struct {
     int64_t n;
     const double* x;
@@ -95,11 +97,16 @@ typedef struct {
     int slip;           /* 0: slip traction implicit in the Stokes solve; 1: lagged by one
                            interface iteration as printed in the algorithm */
     int prec;           /* sdbie_precision of the pair sums in the solves */
-    double tol_mixed;   /* SDBIE_MIXED: relative tolerance of each float-pair correction solve */
-    int refine_max;     /* SDBIE_MIXED: maximum refinement steps */
-    int mixed_mode;     /* SDBIE_MIXED with outer = 1: 0 = refine every local solve (double
-                           residual of the Darcy / Stokes equation); 1 = refine the coupled
-                           system (double residual of both equations, float-pair D-N corrections) */
+    double tol_mixed;   /* SDBIE_MIXED: mixed_mode 0 and 1: relative tolerance of each float-pair
+                           correction solve; mixed_mode 2: relative residual below which the
+                           GMRES products switch to float pairs */
+    int refine_max;     /* SDBIE_MIXED, mixed_mode 0 and 1: maximum refinement steps */
+    int mixed_mode;     /* SDBIE_MIXED: 0 = iterative refinement of every local solve (double
+                           residual, float-pair correction solves); 1 = (outer = 1 only) refinement
+                           of the coupled system (double residual of both equations, float-pair
+                           D-N corrections); 2 = relaxed GMRES in every local solve (double-pair
+                           products until the residual reaches tol_mixed, float pairs after it,
+                           convergence decided by a double-pair true residual) */
 } sdbie_opts;
 
 typedef struct {
@@ -117,20 +124,21 @@ typedef struct sdbie_plan_s* sdbie_plan;
 
 /* Fill `o` with the defaults: tol_gmres 1e-10, tol_ddm 1e-8, theta 0.5,
  * maxit_gmres 500, restart 50, maxit_ddm 200, outer 1, slip 0, prec FP64,
- * tol_mixed 1e-5, refine_max 8, mixed_mode 0. */
+ * tol_mixed 1e-4, refine_max 8, mixed_mode 2. */
 void sdbie_default_opts(sdbie_opts* o);
 
 /* Bytes of device workspace a plan for n nodes (1 <= n <= 2^23) and GMRES
  * restart length up to max_restart (1..200) needs (0 if the arguments are
- * invalid).  Roughly 8 (30 + 3 max_restart) n bytes plus (n/256)^2 * 2. */
+ * invalid).  Roughly 8 (30 + 3 max_restart) n + 128 n bytes plus (n/256)^2 * 2. */
 size_t sdbie_workspace_bytes(int64_t n, int max_restart);
 
 /* Stage a surface: spatial (Morton) ordering, double and float copies of the
  * node data, tile bounds.  `ws` (device, 256-byte aligned, ws_bytes >=
  * sdbie_workspace_bytes(s->n, max_restart)) must stay valid until the plan is
  * destroyed; the node arrays of `s` are copied and may be freed afterwards.
- * Synchronises `stream`.  Errors: ERR_ARG, ERR_WORKSPACE, ERR_NONFINITE
- * (non-finite node data or weights), ERR_DEVICE. */
+ * Synchronises `stream`.  Errors: ERR_ARG (also coordinates or delta out of
+ * the accepted range), ERR_WORKSPACE, ERR_NONFINITE (non-finite node data or
+ * weights), ERR_DEVICE. */
 int sdbie_plan_create(sdbie_plan* plan, const sdbie_surface* s, int max_restart,
                       void* ws, size_t ws_bytes, void* stream);
 int sdbie_plan_destroy(sdbie_plan plan);

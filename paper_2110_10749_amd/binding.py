@@ -159,6 +159,8 @@ def default_opts(**kw) -> Opts:
             v = {"sa": 0, "gmres": 1}[v]
         if k == "slip" and isinstance(v, str):
             v = {"implicit": 0, "lagged": 1}[v]
+        if k == "mixed_mode" and isinstance(v, str):
+            v = {"refine": 0, "coupled": 1, "relaxed": 2}[v]
         setattr(o, k, v)
     return o
 

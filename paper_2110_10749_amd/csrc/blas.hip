@@ -134,9 +134,12 @@ __global__ void k_scatter(int64_t n, int comps, const int32_t* __restrict__ perm
     for (int c = 0; c < comps; ++c) dst[c * n + o] = src[c * n + i];
 }
 
-__global__ void k_check_finite(const double* __restrict__ a, int64_t len, int* __restrict__ flag) {
+// flag[0] = 1 if some entry is not finite, flag[1] = 1 if some finite entry exceeds bound in magnitude
+__global__ void k_check_finite(const double* __restrict__ a, int64_t len, double bound, int* __restrict__ flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < len && !isfinite(a[i])) flag[0] = 1;
+    if (i >= len) return;
+    if (!isfinite(a[i])) flag[0] = 1;
+    else if (fabs(a[i]) > bound) flag[1] = 1;
 }
 
 // ---- adjoint helpers ------------------------------------------------------
@@ -271,8 +274,8 @@ void dev_scatter(const Plan& P, const double* src, double* dst, int comps, hipSt
     SDBIE_LAUNCHED();
 }
 
-void dev_check_finite(const double* a, int64_t len, int* flag, hipStream_t s) {
-    hipLaunchKernelGGL(k_check_finite, dim3(nblk(len)), dim3(256), 0, s, a, len, flag);
+void dev_check_finite(const double* a, int64_t len, double bound, int* flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_check_finite, dim3(nblk(len)), dim3(256), 0, s, a, len, bound, flag);
     SDBIE_LAUNCHED();
 }
 

@@ -23,7 +23,7 @@ int64_t next_pow2(int64_t n) {
 }
 
 struct Layout {
-    size_t x, nrm, w, wn, px, pn, pw, px32, boxes, mask64, mask32, perm, keys, partial, red, scal, vecs,
+    size_t x, nrm, w, wn, px, pn, pw, px32, boxes, mask64, mask32, perm, keys, partial, rec, red, scal, vecs,
         basis_in, basis_out, total;
 };
 
@@ -51,6 +51,7 @@ Layout layout(int64_t n, int m) {
     L.perm = take(n * sizeof(int32_t));
     L.keys = take(next_pow2(n) * sizeof(uint64_t));
     L.partial = take((size_t)2 * choose_splits(n) * 3 * n * d);
+    L.rec = take((size_t)npad * kRecBytes);
     L.red = take((size_t)kRedBlocks * (m + 2) * d);
     L.scal = take((size_t)(kScalGmres + 6 * (m + 2) + 64 > 1024 ? kScalGmres + 6 * (m + 2) + 64 : 1024) * d);
     L.vecs = take((size_t)kNumVec * 3 * n * d);
@@ -93,7 +94,7 @@ sdbie_opts checked_opts(const sdbie_opts* op, const Plan& P) {
     if (o.prec != SDBIE_FP64 && o.prec != SDBIE_MIXED) fail(SDBIE_ERR_ARG, "prec must be SDBIE_FP64 or SDBIE_MIXED");
     if (!(o.tol_mixed > 0.0 && o.tol_mixed < 1.0)) fail(SDBIE_ERR_ARG, "tol_mixed must lie in (0, 1)");
     if (o.refine_max < 1) fail(SDBIE_ERR_ARG, "refine_max must be >= 1");
-    if (o.mixed_mode != 0 && o.mixed_mode != 1) fail(SDBIE_ERR_ARG, "mixed_mode must be 0 or 1");
+    if (o.mixed_mode < 0 || o.mixed_mode > 2) fail(SDBIE_ERR_ARG, "mixed_mode must be 0, 1 or 2");
     return o;
 }
 
@@ -144,6 +145,7 @@ void carve_workspace(Plan& P, void* ws) {
     P.keys = reinterpret_cast<uint64_t*>(b + L.keys);
     P.npow2 = next_pow2(P.n);
     P.partial = reinterpret_cast<double*>(b + L.partial);
+    P.rec = b + L.rec;
     P.red = reinterpret_cast<double*>(b + L.red);
     P.scal = reinterpret_cast<double*>(b + L.scal);
     P.vecs = reinterpret_cast<double*>(b + L.vecs);
@@ -168,9 +170,9 @@ void sdbie_default_opts(sdbie_opts* o) {
     o->outer = 1;
     o->slip = 0;
     o->prec = SDBIE_FP64;
-    o->tol_mixed = 1e-5;
+    o->tol_mixed = 1e-4;
     o->refine_max = 8;
-    o->mixed_mode = 0;
+    o->mixed_mode = 2;
 }
 
 size_t sdbie_workspace_bytes(int64_t n, int max_restart) {
@@ -190,6 +192,7 @@ int sdbie_plan_create(sdbie_plan* out, const sdbie_surface* s, int max_restart, 
         if (!s || !s->x || !s->nrm || !s->w) fail(SDBIE_ERR_ARG, "null surface array");
         if (s->n < 1 || s->n > kMaxNodes) fail(SDBIE_ERR_ARG, "n must lie in [1, 2^23]");
         check_finite_pos(s->delta, "delta");
+        if (s->delta < kMinDelta || s->delta > kMaxCoord) fail(SDBIE_ERR_ARG, "delta must lie in [1e-15, 1e15]");
         if (max_restart < 1 || max_restart > 200) fail(SDBIE_ERR_ARG, "max_restart must lie in [1, 200]");
         if (!ws) fail(SDBIE_ERR_WORKSPACE, "null workspace");
         if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) fail(SDBIE_ERR_WORKSPACE, "workspace not 256-byte aligned");

@@ -32,6 +32,11 @@ constexpr int kTile = 256;       // sources staged in LDS per tile
 constexpr int kMaxSplit = 64;    // source splits of one pair pass
 constexpr int64_t kMaxNodes = (int64_t)1 << 23;  // the tile-pair masks grow as (n/256)^2 bytes
 constexpr int kNearUnit = 64;    // sources per work unit of the near-field kernel
+constexpr int kRecBytes = 128;   // largest per-source record of a pair pass
+// accepted input range: |coordinates| <= kMaxCoord, delta in [kMinDelta, kMaxCoord],
+// so every pair distance squared is a normal number in float and double
+constexpr double kMaxCoord = 1e15;
+constexpr double kMinDelta = 1e-15;
 constexpr int kRedBlocks = 512;  // blocks of the deterministic reductions
 
 // Pair-sum passes --------------------------------------------------------------
@@ -101,12 +106,15 @@ struct Plan {
     int64_t npow2 = 0;
     // scratch
     double* partial = nullptr;  // [2 * nsplit][3][n]: far splits then near splits
+    void* rec = nullptr;        // per-pass source records, [npad][kRecBytes]
     double* red = nullptr;      // reduction partials [kRedBlocks * 64]
     double* scal = nullptr;     // small device scalars / columns [256]
     double* vecs = nullptr;     // general work vectors, kNumVec x [3][n]
     double* basis_in = nullptr;   // inner GMRES basis [(max_restart+1)][3n]
     double* basis_out = nullptr;  // outer GMRES basis [(max_restart+1)][n]
     double* host_pinned = nullptr;  // not used (host buffers are plain)
+    // (target, source) pairs of real nodes in the near tile pairs (double, float masks)
+    double near_pairs64 = 0.0, near_pairs32 = 0.0;
     // bookkeeping for info
     int64_t applies_fp64 = 0, applies_mixed = 0;
     double pairs = 0.0;
@@ -125,7 +133,7 @@ void launch_grad_pass(const Plan& P, const GradDesc& g, hipStream_t s);
 int choose_splits(int64_t n);
 
 // kernel timing (profile.hip)
-int prof_variant(int family, bool mixed, int code);
+int prof_variant(int family, bool mixed, int code, int part);
 struct ProfScope {
     ProfScope(int variant, double pairs, hipStream_t s);
     ~ProfScope();
@@ -161,7 +169,7 @@ void dev_traction(const Plan& P, const double* p, const double* u, double beta, 
 void dev_gather(const Plan& P, const double* src, double* dst, int comps, hipStream_t s);
 void dev_scatter(const Plan& P, const double* src, double* dst, int comps, hipStream_t s);
 // non-finite check: *flag (device int) set to 1 if any element is not finite
-void dev_check_finite(const double* a, int64_t len, int* flag, hipStream_t s);
+void dev_check_finite(const double* a, int64_t len, double bound, int* flag, hipStream_t s);
 
 // adjoint helpers (see blas.hip)
 void dev_adj_darcy(const Plan& P, const double* tn, const double* lam, const double* dl1, const double* sum,

@@ -37,6 +37,18 @@ constexpr double kPiD = 3.14159265358979323846;
 
 __device__ __forceinline__ double rsq(double v) { return rsqrt(v); }
 __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
+// 1/sqrt(v) for finite v > 0 away from the denormal range (far-field r^2):
+// the hardware estimate y refined by the second-order expansion of
+// (1 - e)^(-1/2) = 1 + e/2 + 3e^2/8 + ..., e = 1 - v y^2.  No special cases.
+__device__ __forceinline__ double rsq_pos(double v) {
+    const double y = __builtin_amdgcn_rsq(v);
+    const double e = fma(-v * y, y, 1.0);
+    return fma(y * e, fma(e, 0.375, 0.5), y);
+}
+__device__ __forceinline__ float rsq_pos(float v) { return __builtin_amdgcn_rsqf(v); }
+// far-field pairs never reach r = 0; near-field pairs do (the self pair)
+template <bool NEAR, typename T>
+__device__ __forceinline__ T rsq_pair(T v) { return NEAR ? rsq(v) : rsq_pos(v); }
 __device__ __forceinline__ double erf_t(double v) { return erf(v); }
 __device__ __forceinline__ float erf_t(float v) { return erff(v); }
 __device__ __forceinline__ double exp_t(double v) { return exp(v); }
@@ -113,6 +125,7 @@ struct KArgs {
     double inv_delta;
     double rc2;         // (rho_cut * delta)^2
     double* partial;    // [2 nsplit][C][n]
+    void* rec;          // source records of the pass [npad][Op::R] (T)
     int unit_w;         // sources enter with weight 1 (transposed single layers)
     const double* dl_tgt;  // target density of the subtracted double layer (nullable: dl_dens)
     // position-gradient pass
@@ -132,54 +145,71 @@ __device__ __forceinline__ double src_weight(const KArgs& a, int64_t j) {
     return a.unit_w ? (j < a.n ? 1.0 : 0.0) : a.w[j];
 }
 
+// Source records.  Before the pair kernels of a pass, one thread per source
+// packs what every pair with that source needs (coordinates, weighted normal,
+// densities, premultiplied by the quadrature weight and the kernel constant)
+// into a record of R elements of T.  The pair kernels read the records at
+// wave-uniform addresses, so they arrive through the scalar cache in SGPRs
+// and enter the vector ALU as scalar operands: no LDS, no barriers.
+// U records (a power of two, at most 256 bytes) are read per unrolled step.
+template <typename T, int R>
+struct alignas(16) Record {
+    T v[R];
+};
+
+template <typename T, int R>
+__host__ __device__ constexpr int unroll_of() {
+    int u = 1;  // largest power of two with u records in 256 bytes
+    while (2 * u * R * (int)sizeof(T) <= 256) u *= 2;
+    return u;
+}
+
 // --------------------------------------------------------------------------
 // Laplace: DL term c_dl * w_j (q_j - SUB q_i) (D.n_j) s2/r^3, SL term c_sl * w_j g_j s1/r
+// record: x y z q | nx ny nz g   (SL only: x y z g); n and g carry c w_j
 // --------------------------------------------------------------------------
 template <typename T, bool DL, bool SL, bool SUB>
 struct LaplaceOp {
     static constexpr int C = 1;
-    static constexpr int TD = DL ? kTile : 1, TS = SL ? kTile : 1;
-    struct Smem {
-        T x[kTile], y[kTile], z[kTile];
-        T nx[TD], ny[TD], nz[TD], q[TD];
-        T g[TS];
-    };
+    static constexpr int R = DL ? 8 : 4;
+    static constexpr int U = unroll_of<T, R>();
+    static constexpr int Q = 3, NX = 4, NY = 5, NZ = 6, G = DL ? 7 : 3;
     T xi, yi, zi, qi;
     double acc = 0.0;
     T tacc = T(0);
 
+    __device__ __forceinline__ static void pack(T* r, int64_t j, const KArgs& a) {
+        r[0] = load_x<T>(a, 0, j);
+        r[1] = load_x<T>(a, 1, j);
+        r[2] = load_x<T>(a, 2, j);
+        const double wj = src_weight(a, j);
+        if (DL) {
+            const double c = a.c_dl * wj;
+            r[NX] = T(c * a.nrm[j]);
+            r[NY] = T(c * a.nrm[a.npad + j]);
+            r[NZ] = T(c * a.nrm[2 * a.npad + j]);
+            r[Q] = T(dens_at(a.dl_dens, a.n, 0, j));
+        }
+        r[G] = SL ? T(a.c_sl * wj * dens_at(a.sl_dens, a.n, 0, j)) : T(0);
+    }
     __device__ __forceinline__ void init(const KArgs& a, int64_t i) {
         xi = load_x<T>(a, 0, i);
         yi = load_x<T>(a, 1, i);
         zi = load_x<T>(a, 2, i);
         qi = (DL && SUB) ? T(dens_at(a.dl_dens, a.n, 0, i)) : T(0);
     }
-    __device__ __forceinline__ void load(Smem& s, int t, int64_t j, const KArgs& a) const {
-        s.x[t] = load_x<T>(a, 0, j);
-        s.y[t] = load_x<T>(a, 1, j);
-        s.z[t] = load_x<T>(a, 2, j);
-        const double wj = src_weight(a, j);
-        if (DL) {
-            const double c = a.c_dl * wj;
-            s.nx[t] = T(c * a.nrm[j]);
-            s.ny[t] = T(c * a.nrm[a.npad + j]);
-            s.nz[t] = T(c * a.nrm[2 * a.npad + j]);
-            s.q[t] = T(dens_at(a.dl_dens, a.n, 0, j));
-        }
-        if (SL) s.g[t] = T(a.c_sl * wj * dens_at(a.sl_dens, a.n, 0, j));
-    }
     template <bool NEAR>
-    __device__ __forceinline__ void pair(const Smem& s, int jj, T id, T id2, T rc2) {
-        const T dx = xi - s.x[jj], dy = yi - s.y[jj], dz = zi - s.z[jj];
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        const T inv_r = rsq(r2);
+    __device__ __forceinline__ void pair(const T* r, T id, T id2, T rc2) {
+        const T dx = xi - r[0], dy = yi - r[1], dz = zi - r[2];
+        const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const T inv_r = rsq_pair<NEAR>(r2);
         T k1 = inv_r, k2 = inv_r * inv_r * inv_r, k3, k4;
         if (NEAR && r2 < rc2) near_factors<T, SL, DL, false, false>(r2, inv_r, id, id2, k1, k2, k3, k4);
         if (DL) {
-            const T dn = dx * s.nx[jj] + dy * s.ny[jj] + dz * s.nz[jj];
-            tacc += (s.q[jj] - qi) * dn * k2;
+            const T dn = fma(dx, r[NX], fma(dy, r[NY], dz * r[NZ]));
+            tacc = fma((r[Q] - qi) * dn, k2, tacc);
         }
-        if (SL) tacc += s.g[jj] * k1;
+        if (SL) tacc = fma(r[G], k1, tacc);
     }
     __device__ __forceinline__ void flush() {
         acc += (double)tacc;
@@ -194,36 +224,25 @@ struct LaplaceOp {
 // Stokes: DL term c_dl w_j ((u_j - SUB u_i).D)(D.n_j) D s4/r^5,
 //         SL term c_sl w_j [f_j s1/r + D (D.f_j) s3/r^3],
 //         f_j = sl_dens_j, or beta (u_j - (u_j.n_j) n_j) when SLIP.
+// record: x y z nx | ny nz ux uy | uz fx fy fz   (SL only: x y z fx | fy fz 0 0)
+// The two terms along D share one coefficient: acc += f k1 + (cDL + cSL) D.
 // --------------------------------------------------------------------------
 template <typename T, bool DL, bool SL, bool SUB, bool SLIP>
 struct StokesOp {
     static constexpr int C = 3;
-    static constexpr int TD = DL ? kTile : 1, TS = SL ? kTile : 1;
-    struct Smem {
-        T x[kTile], y[kTile], z[kTile];
-        T nx[TD], ny[TD], nz[TD], ux[TD], uy[TD], uz[TD];
-        T fx[TS], fy[TS], fz[TS];
-    };
+    static constexpr int R = DL ? 12 : 8;
+    static constexpr int U = unroll_of<T, R>();
+    static constexpr int NX = 3, NY = 4, NZ = 5, UX = 6, UY = 7, UZ = 8;
+    static constexpr int FX = DL ? 9 : 3, FY = FX + 1, FZ = FX + 2;
     T xi, yi, zi, uix = T(0), uiy = T(0), uiz = T(0);
     double ax = 0.0, ay = 0.0, az = 0.0;
     T tx = T(0), ty = T(0), tz = T(0);
 
-    __device__ __forceinline__ void init(const KArgs& a, int64_t i) {
-        xi = load_x<T>(a, 0, i);
-        yi = load_x<T>(a, 1, i);
-        zi = load_x<T>(a, 2, i);
-        if (DL && SUB) {
-            const double* tg = a.dl_tgt ? a.dl_tgt : a.dl_dens;
-            uix = T(dens_at(tg, a.n, 0, i));
-            uiy = T(dens_at(tg, a.n, 1, i));
-            uiz = T(dens_at(tg, a.n, 2, i));
-        }
-    }
-    __device__ __forceinline__ void load(Smem& s, int t, int64_t j, const KArgs& a) const {
+    __device__ __forceinline__ static void pack(T* r, int64_t j, const KArgs& a) {
         const int64_t np = a.npad;
-        s.x[t] = load_x<T>(a, 0, j);
-        s.y[t] = load_x<T>(a, 1, j);
-        s.z[t] = load_x<T>(a, 2, j);
+        r[0] = load_x<T>(a, 0, j);
+        r[1] = load_x<T>(a, 1, j);
+        r[2] = load_x<T>(a, 2, j);
         const double wj = src_weight(a, j);
         const double nx = a.nrm[j], ny = a.nrm[np + j], nz = a.nrm[2 * np + j];
         double ux = 0.0, uy = 0.0, uz = 0.0;
@@ -234,12 +253,14 @@ struct StokesOp {
         }
         if (DL) {
             const double c = a.c_dl * wj;
-            s.nx[t] = T(c * nx);
-            s.ny[t] = T(c * ny);
-            s.nz[t] = T(c * nz);
-            s.ux[t] = T(ux);
-            s.uy[t] = T(uy);
-            s.uz[t] = T(uz);
+            r[NX] = T(c * nx);
+            r[NY] = T(c * ny);
+            r[NZ] = T(c * nz);
+            r[UX] = T(ux);
+            r[UY] = T(uy);
+            r[UZ] = T(uz);
+        } else {
+            r[6] = r[7] = T(0);  // padding of the single-layer record
         }
         if (SL) {
             double fx, fy, fz;
@@ -254,35 +275,49 @@ struct StokesOp {
                 fz = dens_at(a.sl_dens, a.n, 2, j);
             }
             const double c = a.c_sl * wj;
-            s.fx[t] = T(c * fx);
-            s.fy[t] = T(c * fy);
-            s.fz[t] = T(c * fz);
+            r[FX] = T(c * fx);
+            r[FY] = T(c * fy);
+            r[FZ] = T(c * fz);
+        } else {
+            r[FX] = r[FY] = r[FZ] = T(0);
+        }
+    }
+    __device__ __forceinline__ void init(const KArgs& a, int64_t i) {
+        xi = load_x<T>(a, 0, i);
+        yi = load_x<T>(a, 1, i);
+        zi = load_x<T>(a, 2, i);
+        if (DL && SUB) {
+            const double* tg = a.dl_tgt ? a.dl_tgt : a.dl_dens;
+            uix = T(dens_at(tg, a.n, 0, i));
+            uiy = T(dens_at(tg, a.n, 1, i));
+            uiz = T(dens_at(tg, a.n, 2, i));
         }
     }
     template <bool NEAR>
-    __device__ __forceinline__ void pair(const Smem& s, int jj, T id, T id2, T rc2) {
-        const T dx = xi - s.x[jj], dy = yi - s.y[jj], dz = zi - s.z[jj];
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        const T inv_r = rsq(r2);
+    __device__ __forceinline__ void pair(const T* r, T id, T id2, T rc2) {
+        const T dx = xi - r[0], dy = yi - r[1], dz = zi - r[2];
+        const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const T inv_r = rsq_pair<NEAR>(r2);
         const T ir2 = inv_r * inv_r;
         T k1 = inv_r, k2, k3 = inv_r * ir2, k4 = k3 * ir2;
         if (NEAR && r2 < rc2) near_factors<T, SL, false, SL, DL>(r2, inv_r, id, id2, k1, k2, k3, k4);
+        T cd = T(0);
         if (DL) {
-            const T ux = s.ux[jj] - uix, uy = s.uy[jj] - uiy, uz = s.uz[jj] - uiz;
-            const T ud = ux * dx + uy * dy + uz * dz;
-            const T dn = dx * s.nx[jj] + dy * s.ny[jj] + dz * s.nz[jj];
-            const T c = ud * dn * k4;
-            tx += c * dx;
-            ty += c * dy;
-            tz += c * dz;
+            const T ux = r[UX] - uix, uy = r[UY] - uiy, uz = r[UZ] - uiz;
+            const T ud = fma(ux, dx, fma(uy, dy, uz * dz));
+            const T dn = fma(dx, r[NX], fma(dy, r[NY], dz * r[NZ]));
+            cd = ud * dn * k4;
         }
         if (SL) {
-            const T fx = s.fx[jj], fy = s.fy[jj], fz = s.fz[jj];
-            const T c = (dx * fx + dy * fy + dz * fz) * k3;
-            tx += fx * k1 + c * dx;
-            ty += fy * k1 + c * dy;
-            tz += fz * k1 + c * dz;
+            const T fx = r[FX], fy = r[FY], fz = r[FZ];
+            cd = fma(fma(dx, fx, fma(dy, fy, dz * fz)), k3, cd);
+            tx = fma(fx, k1, tx);
+            ty = fma(fy, k1, ty);
+            tz = fma(fz, k1, tz);
         }
+        tx = fma(cd, dx, tx);
+        ty = fma(cd, dy, ty);
+        tz = fma(cd, dz, tz);
     }
     __device__ __forceinline__ void flush() {
         ax += (double)tx;
@@ -299,20 +334,25 @@ struct StokesOp {
 };
 
 // --------------------------------------------------------------------------
-// Transposed double layers (adjoint): the double-layer kernel contracted with
-// the TARGET's normal, sources weighted by c_dl (times w_j unless unit_w):
-//   Laplace:  out_i = n_i . sum_j c_dl w_j q_j D s2/r^3
-//   Stokes:   out_i = sum_j c_dl w_j (D.q_j)(D.n_i) D s4/r^5
+// Transposed double layers (adjoint): the normal is the target's and the
+// density carries the source weight factor.
+//   Laplace:  out_i = sum_j c w_j q_j (D.n_i) s2/r^3       record: x y z cwq
+//   Stokes:   out_i = sum_j c w_j (q_j.D)(D.n_i) D s4/r^5  record: x y z cwqx | cwqy cwqz 0 0
 // --------------------------------------------------------------------------
 template <typename T>
 struct LaplaceTNOp {
     static constexpr int C = 1;
-    struct Smem {
-        T x[kTile], y[kTile], z[kTile], q[kTile];
-    };
+    static constexpr int R = 4;
+    static constexpr int U = unroll_of<T, R>();
     T xi, yi, zi, nxi, nyi, nzi;
     double acc = 0.0;
     T tacc = T(0);
+    __device__ __forceinline__ static void pack(T* r, int64_t j, const KArgs& a) {
+        r[0] = load_x<T>(a, 0, j);
+        r[1] = load_x<T>(a, 1, j);
+        r[2] = load_x<T>(a, 2, j);
+        r[3] = T(a.c_dl * src_weight(a, j) * dens_at(a.dl_dens, a.n, 0, j));
+    }
     __device__ __forceinline__ void init(const KArgs& a, int64_t i) {
         xi = load_x<T>(a, 0, i);
         yi = load_x<T>(a, 1, i);
@@ -321,20 +361,15 @@ struct LaplaceTNOp {
         nyi = T(a.nrm[a.npad + i]);
         nzi = T(a.nrm[2 * a.npad + i]);
     }
-    __device__ __forceinline__ void load(Smem& s, int t, int64_t j, const KArgs& a) const {
-        s.x[t] = load_x<T>(a, 0, j);
-        s.y[t] = load_x<T>(a, 1, j);
-        s.z[t] = load_x<T>(a, 2, j);
-        s.q[t] = T(a.c_dl * src_weight(a, j) * dens_at(a.dl_dens, a.n, 0, j));
-    }
     template <bool NEAR>
-    __device__ __forceinline__ void pair(const Smem& s, int jj, T id, T id2, T rc2) {
-        const T dx = xi - s.x[jj], dy = yi - s.y[jj], dz = zi - s.z[jj];
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        const T inv_r = rsq(r2);
+    __device__ __forceinline__ void pair(const T* r, T id, T id2, T rc2) {
+        const T dx = xi - r[0], dy = yi - r[1], dz = zi - r[2];
+        const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const T inv_r = rsq_pair<NEAR>(r2);
         T k1, k2 = inv_r * inv_r * inv_r, k3, k4;
         if (NEAR && r2 < rc2) near_factors<T, false, true, false, false>(r2, inv_r, id, id2, k1, k2, k3, k4);
-        tacc += s.q[jj] * (dx * nxi + dy * nyi + dz * nzi) * k2;
+        const T dn = fma(dx, nxi, fma(dy, nyi, dz * nzi));
+        tacc = fma(r[3] * dn, k2, tacc);
     }
     __device__ __forceinline__ void flush() {
         acc += (double)tacc;
@@ -348,12 +383,21 @@ struct LaplaceTNOp {
 template <typename T>
 struct StokesTNOp {
     static constexpr int C = 3;
-    struct Smem {
-        T x[kTile], y[kTile], z[kTile], qx[kTile], qy[kTile], qz[kTile];
-    };
+    static constexpr int R = 8;
+    static constexpr int U = unroll_of<T, R>();
     T xi, yi, zi, nxi, nyi, nzi;
     double ax = 0.0, ay = 0.0, az = 0.0;
     T tx = T(0), ty = T(0), tz = T(0);
+    __device__ __forceinline__ static void pack(T* r, int64_t j, const KArgs& a) {
+        r[0] = load_x<T>(a, 0, j);
+        r[1] = load_x<T>(a, 1, j);
+        r[2] = load_x<T>(a, 2, j);
+        const double c = a.c_dl * src_weight(a, j);
+        r[3] = T(c * dens_at(a.dl_dens, a.n, 0, j));
+        r[4] = T(c * dens_at(a.dl_dens, a.n, 1, j));
+        r[5] = T(c * dens_at(a.dl_dens, a.n, 2, j));
+        r[6] = r[7] = T(0);
+    }
     __device__ __forceinline__ void init(const KArgs& a, int64_t i) {
         xi = load_x<T>(a, 0, i);
         yi = load_x<T>(a, 1, i);
@@ -362,28 +406,19 @@ struct StokesTNOp {
         nyi = T(a.nrm[a.npad + i]);
         nzi = T(a.nrm[2 * a.npad + i]);
     }
-    __device__ __forceinline__ void load(Smem& s, int t, int64_t j, const KArgs& a) const {
-        s.x[t] = load_x<T>(a, 0, j);
-        s.y[t] = load_x<T>(a, 1, j);
-        s.z[t] = load_x<T>(a, 2, j);
-        const double c = a.c_dl * src_weight(a, j);
-        s.qx[t] = T(c * dens_at(a.dl_dens, a.n, 0, j));
-        s.qy[t] = T(c * dens_at(a.dl_dens, a.n, 1, j));
-        s.qz[t] = T(c * dens_at(a.dl_dens, a.n, 2, j));
-    }
     template <bool NEAR>
-    __device__ __forceinline__ void pair(const Smem& s, int jj, T id, T id2, T rc2) {
-        const T dx = xi - s.x[jj], dy = yi - s.y[jj], dz = zi - s.z[jj];
-        const T r2 = dx * dx + dy * dy + dz * dz;
-        const T inv_r = rsq(r2);
+    __device__ __forceinline__ void pair(const T* r, T id, T id2, T rc2) {
+        const T dx = xi - r[0], dy = yi - r[1], dz = zi - r[2];
+        const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const T inv_r = rsq_pair<NEAR>(r2);
         const T ir2 = inv_r * inv_r;
         T k1, k2, k3, k4 = inv_r * ir2 * ir2;
         if (NEAR && r2 < rc2) near_factors<T, false, false, false, true>(r2, inv_r, id, id2, k1, k2, k3, k4);
-        const T dq = dx * s.qx[jj] + dy * s.qy[jj] + dz * s.qz[jj];
-        const T c = dq * (dx * nxi + dy * nyi + dz * nzi) * k4;
-        tx += c * dx;
-        ty += c * dy;
-        tz += c * dz;
+        const T dq = fma(dx, r[3], fma(dy, r[4], dz * r[5]));
+        const T c = dq * fma(dx, nxi, fma(dy, nyi, dz * nzi)) * k4;
+        tx = fma(c, dx, tx);
+        ty = fma(c, dy, ty);
+        tz = fma(c, dz, tz);
     }
     __device__ __forceinline__ void flush() {
         ax += (double)tx;
@@ -467,7 +502,7 @@ __device__ __forceinline__ void grad_pair(const GTgt& t, const GSrc& s, const KA
                                           double rc2, double& gx, double& gy, double& gz) {
     const double dx = t.x - s.x, dy = t.y - s.y, dz = t.z - s.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const double inv_r = rsqrt(r2);
+    const double inv_r = rsq_pair<NEAR>(r2);
     const double ir2 = inv_r * inv_r;
     double k1, k2 = inv_r * ir2, k3 = k2, k4 = k2 * ir2;
     double g2 = 3.0 * k4, g4 = 5.0 * k4 * ir2;
@@ -496,51 +531,52 @@ __device__ __forceinline__ void grad_pair(const GTgt& t, const GSrc& s, const KA
     gz += cD * dz + cN * s.nz + cA * azv + cL * t.lz + cF * s.fz;
 }
 
-// SWAP = false: the lane is the target i and the tile holds sources j;
-// SWAP = true: the lane is the source j and the tile holds targets i.
+// SWAP = false: the lane is the target i and the records are sources j;
+// SWAP = true: the lane is the source j and the records are targets i.
+// record (double): the GSrc fields (15, padded to 16) or the GTgt fields (11, padded to 12)
 template <bool SWAP>
 struct GradOp {
     static constexpr int C = 3;
-    struct Smem {
-        double f[SWAP ? 11 : 15][kTile];
-    };
+    static constexpr int R = SWAP ? 12 : 16;
+    static constexpr int U = unroll_of<double, R>();
     GTgt t;
     GSrc s;
     double ax = 0.0, ay = 0.0, az = 0.0;
     const KArgs* ap;
+    __device__ __forceinline__ static void pack(double* r, int64_t j, const KArgs& a) {
+        if (SWAP) {
+            const GTgt q = load_gtgt(a, j);
+            const double v[12] = {q.x, q.y, q.z, q.p, q.ux, q.uy, q.uz, q.l1, q.lx, q.ly, q.lz, 0.0};
+#pragma unroll
+            for (int f = 0; f < 12; ++f) r[f] = v[f];
+        } else {
+            const GSrc q = load_gsrc(a, j);
+            const double v[16] = {q.x, q.y, q.z, q.nx, q.ny, q.nz, q.w, q.p, q.v, q.ux, q.uy, q.uz,
+                                  q.fx, q.fy, q.fz, 0.0};
+#pragma unroll
+            for (int f = 0; f < 16; ++f) r[f] = v[f];
+        }
+    }
     __device__ __forceinline__ void init(const KArgs& a, int64_t i) {
         ap = &a;
         if (SWAP) s = load_gsrc(a, i);
         else t = load_gtgt(a, i);
     }
-    __device__ __forceinline__ void load(Smem& sm, int k, int64_t j, const KArgs& a) const {
-        if (SWAP) {
-            const GTgt q = load_gtgt(a, j);
-            const double v[11] = {q.x, q.y, q.z, q.p, q.ux, q.uy, q.uz, q.l1, q.lx, q.ly, q.lz};
-#pragma unroll
-            for (int f = 0; f < 11; ++f) sm.f[f][k] = v[f];
-        } else {
-            const GSrc q = load_gsrc(a, j);
-            const double v[15] = {q.x, q.y, q.z, q.nx, q.ny, q.nz, q.w, q.p, q.v, q.ux, q.uy, q.uz, q.fx, q.fy, q.fz};
-#pragma unroll
-            for (int f = 0; f < 15; ++f) sm.f[f][k] = v[f];
-        }
-    }
     template <bool NEAR>
-    __device__ __forceinline__ void pair(const Smem& sm, int jj, double id, double id2, double rc2) {
+    __device__ __forceinline__ void pair(const double* r, double id, double id2, double rc2) {
         if (SWAP) {
             GTgt q;
-            q.x = sm.f[0][jj]; q.y = sm.f[1][jj]; q.z = sm.f[2][jj]; q.p = sm.f[3][jj];
-            q.ux = sm.f[4][jj]; q.uy = sm.f[5][jj]; q.uz = sm.f[6][jj]; q.l1 = sm.f[7][jj];
-            q.lx = sm.f[8][jj]; q.ly = sm.f[9][jj]; q.lz = sm.f[10][jj];
+            q.x = r[0]; q.y = r[1]; q.z = r[2]; q.p = r[3];
+            q.ux = r[4]; q.uy = r[5]; q.uz = r[6]; q.l1 = r[7];
+            q.lx = r[8]; q.ly = r[9]; q.lz = r[10];
             grad_pair<NEAR>(q, s, *ap, id, id2, rc2, ax, ay, az);
         } else {
             GSrc q;
-            q.x = sm.f[0][jj]; q.y = sm.f[1][jj]; q.z = sm.f[2][jj];
-            q.nx = sm.f[3][jj]; q.ny = sm.f[4][jj]; q.nz = sm.f[5][jj]; q.w = sm.f[6][jj];
-            q.p = sm.f[7][jj]; q.v = sm.f[8][jj];
-            q.ux = sm.f[9][jj]; q.uy = sm.f[10][jj]; q.uz = sm.f[11][jj];
-            q.fx = sm.f[12][jj]; q.fy = sm.f[13][jj]; q.fz = sm.f[14][jj];
+            q.x = r[0]; q.y = r[1]; q.z = r[2];
+            q.nx = r[3]; q.ny = r[4]; q.nz = r[5]; q.w = r[6];
+            q.p = r[7]; q.v = r[8];
+            q.ux = r[9]; q.uy = r[10]; q.uz = r[11];
+            q.fx = r[12]; q.fy = r[13]; q.fz = r[14];
             grad_pair<NEAR>(t, q, *ap, id, id2, rc2, ax, ay, az);
         }
     }
@@ -553,12 +589,31 @@ struct GradOp {
     }
 };
 
+static_assert(GradOp<false>::R * sizeof(double) <= kRecBytes, "record larger than its workspace slot");
+
+// One thread per source (padding included): write the pass's source records.
+template <class Op, typename T>
+__global__ __launch_bounds__(256) void pack_sources(KArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= a.npad) return;
+    Record<T, Op::R> rec;
+    Op::pack(rec.v, j, a);
+    reinterpret_cast<Record<T, Op::R>*>(a.rec)[j] = rec;
+}
+
+// NU consecutive records starting at r (wave-uniform address)
+template <class Op, typename T, bool NEAR, int NU>
+__device__ __forceinline__ void pair_group(Op& op, const T* r, T id, T id2, T rc2) {
+#pragma unroll
+    for (int u = 0; u < NU; ++u) op.template pair<NEAR>(r + u * Op::R, id, id2, rc2);
+}
+
 // Far-field pass: block (b, split) sums target tile b against every tile of
 // its split's range whose pairs are all beyond the cutoff (mask 0).  No
 // smoothing code is compiled in: every pair uses the plain 1/r^p kernels.
 template <class Op, typename T>
 __global__ __launch_bounds__(kTPB) void far_pairs(KArgs a) {
-    __shared__ typename Op::Smem sm;
+    static_assert(kTile % Op::U == 0, "unroll must divide the tile");
     const int split = blockIdx.x % a.nsplit;
     const int b = blockIdx.x / a.nsplit;
     const int64_t i = (int64_t)b * kTPB + threadIdx.x;  // < npad
@@ -568,23 +623,26 @@ __global__ __launch_bounds__(kTPB) void far_pairs(KArgs a) {
     const int t0 = split * a.tiles_per_split;
     const int t1 = t0 + a.tiles_per_split < a.ntiles ? t0 + a.tiles_per_split : a.ntiles;
     const uint8_t* row = a.mask + (int64_t)b * a.ntiles;
+    const T* rec = static_cast<const T*>(a.rec);
     for (int t = t0; t < t1; ++t) {
-        if (row[t]) continue;  // block-uniform
-        __syncthreads();
-        op.load(sm, threadIdx.x, (int64_t)t * kTile + threadIdx.x, a);
-        __syncthreads();
-#pragma unroll 8
-        for (int jj = 0; jj < kTile; ++jj) op.template pair<false>(sm, jj, id, id2, rc2);
+        if (row[t]) continue;  // uniform
+        const T* rt = rec + (int64_t)t * kTile * Op::R;
+#pragma unroll 1
+        for (int jj = 0; jj < kTile; jj += Op::U)
+            pair_group<Op, T, false, Op::U>(op, rt + jj * Op::R, id, id2, rc2);
         op.flush();
     }
     if (i < a.n) op.store(a, split, i);
 }
 
-// Near-field pass: block (b, split) walks the near tiles of row b (mask 1) in
-// order, cut into units of kNearUnit sources, and takes every nsplit-th unit.
+// Near-field pass: the tiles of the target tile's mask row, cut into units of
+// kNearUnit sources dealt round-robin to the splits; every pair takes the
+// smoothing branch when r < rho_cut delta.
 template <class Op, typename T>
 __global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
-    __shared__ typename Op::Smem sm;
+    // the double smoothing branch is long: one record per step keeps its registers in bounds
+    constexpr int NU = sizeof(T) == 8 ? 1 : Op::U;
+    static_assert(kNearUnit % NU == 0, "unroll must divide the near unit");
     const int split = blockIdx.x % a.nsplit;
     const int b = blockIdx.x / a.nsplit;
     const int64_t i = (int64_t)b * kTPB + threadIdx.x;
@@ -592,22 +650,22 @@ __global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
     op.init(a, i);
     const T id = T(a.inv_delta), id2 = id * id, rc2 = T(a.rc2);
     const uint8_t* row = a.mask + (int64_t)b * a.ntiles;
+    const T* rec = static_cast<const T*>(a.rec);
     constexpr int kUnits = kTile / kNearUnit;
     int rank = 0;
     const int lane = threadIdx.x & 63;
     for (int c0 = 0; c0 < a.ntiles; c0 += 64) {
         const bool f = (c0 + lane < a.ntiles) && row[c0 + lane];
-        uint64_t bal = __ballot(f);  // identical in every wave of the block
+        uint64_t bal = __ballot(f);  // uniform
         while (bal) {
             const int t = c0 + __ffsll((long long)bal) - 1;
             bal &= bal - 1;
             for (int q = 0; q < kUnits; ++q) {
                 if ((rank * kUnits + q) % a.nsplit != split) continue;
-                __syncthreads();
-                if (threadIdx.x < kNearUnit)
-                    op.load(sm, threadIdx.x, (int64_t)t * kTile + q * kNearUnit + threadIdx.x, a);
-                __syncthreads();
-                for (int jj = 0; jj < kNearUnit; ++jj) op.template pair<true>(sm, jj, id, id2, rc2);
+                const T* ru = rec + ((int64_t)t * kTile + q * kNearUnit) * Op::R;
+#pragma unroll 1
+                for (int jj = 0; jj < kNearUnit; jj += NU)
+                    pair_group<Op, T, true, NU>(op, ru + jj * Op::R, id, id2, rc2);
                 op.flush();
             }
             ++rank;
@@ -616,7 +674,8 @@ __global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
     if (i < a.n) op.store(a, a.nsplit + split, i);
 }
 
-// out_i = sum_s partial[s][c][i] + base_scale*base + comp_scale*(*comp)*vecfac + add[c]
+// Sum the 2 nsplit partial slots of each target in a fixed order, then
+//   out = tw * sum + base_scale * base + comp_scale * comp[0] * (1 or n_i) + add
 template <int C>
 __global__ void epilogue(int64_t n, int nslots, const double* __restrict__ partial,
                          const double* __restrict__ tw,
@@ -660,6 +719,7 @@ KArgs make_args(const Plan& P, const PassDesc& d, int nsplit, double cut) {
     a.inv_delta = 1.0 / P.delta;
     a.rc2 = (cut * P.delta) * (cut * P.delta);
     a.partial = P.partial;
+    a.rec = P.rec;
     a.unit_w = d.unit_src_weight ? 1 : 0;
     a.dl_tgt = d.dl_target;
     a.g_p = a.g_v = a.g_u = a.g_f = a.g_l1 = a.g_l2 = nullptr;
@@ -667,13 +727,29 @@ KArgs make_args(const Plan& P, const PassDesc& d, int nsplit, double cut) {
     return a;
 }
 
+// pack, far and near kernels of one pass, each timed on its own when
+// kernel timing is on (pairs: real-node pairs of the far / near tile pairs)
 template <class Op, typename T>
-void launch_pair_kernels(const KArgs& a, hipStream_t st) {
+void launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int family, int code, bool mixed) {
+    static_assert(Op::R * sizeof(T) <= kRecBytes, "record larger than its workspace slot");
+    const double all = (double)P.n * (double)P.n;
+    const double near = mixed ? P.near_pairs32 : P.near_pairs64;
+    {
+        ProfScope prof(prof_variant(family, mixed, code, 2), 0.0, st);
+        hipLaunchKernelGGL((pack_sources<Op, T>), dim3((unsigned)(a.npad / 256)), dim3(256), 0, st, a);
+        SDBIE_LAUNCHED();
+    }
     const dim3 grid((unsigned)((int64_t)a.ntiles * a.nsplit));
-    hipLaunchKernelGGL((far_pairs<Op, T>), grid, dim3(kTPB), 0, st, a);
-    SDBIE_LAUNCHED();
-    hipLaunchKernelGGL((near_pairs<Op, T>), grid, dim3(kTPB), 0, st, a);
-    SDBIE_LAUNCHED();
+    {
+        ProfScope prof(prof_variant(family, mixed, code, 0), all - near, st);
+        hipLaunchKernelGGL((far_pairs<Op, T>), grid, dim3(kTPB), 0, st, a);
+        SDBIE_LAUNCHED();
+    }
+    {
+        ProfScope prof(prof_variant(family, mixed, code, 1), near, st);
+        hipLaunchKernelGGL((near_pairs<Op, T>), grid, dim3(kTPB), 0, st, a);
+        SDBIE_LAUNCHED();
+    }
 }
 
 }  // namespace
@@ -695,12 +771,11 @@ void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
     const int code = (d.dl ? 1 : 0) | (d.sl ? 2 : 0) | (d.sub ? 4 : 0);
     if (d.target_normal) {
         if (!d.dl || d.sl || d.sub) throw Error(SDBIE_ERR_ARG, "transposed Laplace pass takes a double layer only");
-        ProfScope prof(prof_variant(0, d.mixed, 16 | 1), (double)P.n * (double)P.n, st);
-        if (d.mixed) launch_pair_kernels<LaplaceTNOp<float>, float>(a, st);
-        else launch_pair_kernels<LaplaceTNOp<double>, double>(a, st);
+        if (d.mixed) launch_pair_kernels<LaplaceTNOp<float>, float>(P, a, st, 0, 16 | 1, true);
+        else launch_pair_kernels<LaplaceTNOp<double>, double>(P, a, st, 0, 16 | 1, false);
     } else {
-        ProfScope prof(prof_variant(0, d.mixed, d.sl && !d.dl ? 2 : code), (double)P.n * (double)P.n, st);
-#define SDBIE_LAP(T, DL, SL, SUB) launch_pair_kernels<LaplaceOp<T, DL, SL, SUB>, T>(a, st)
+        const int pc = d.sl && !d.dl ? 2 : code;
+#define SDBIE_LAP(T, DL, SL, SUB) launch_pair_kernels<LaplaceOp<T, DL, SL, SUB>, T>(P, a, st, 0, pc, d.mixed)
         if (!d.mixed) {
             switch (code) {
                 case 1: SDBIE_LAP(double, true, false, false); break;
@@ -742,12 +817,11 @@ void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
     const int code = (d.dl ? 1 : 0) | (d.sl ? 2 : 0) | (d.sub ? 4 : 0) | (slip ? 8 : 0);
     if (d.target_normal) {
         if (!d.dl || d.sl || d.sub) throw Error(SDBIE_ERR_ARG, "transposed Stokes pass takes a double layer only");
-        ProfScope prof(prof_variant(1, d.mixed, 16 | 1), (double)P.n * (double)P.n, st);
-        if (d.mixed) launch_pair_kernels<StokesTNOp<float>, float>(a, st);
-        else launch_pair_kernels<StokesTNOp<double>, double>(a, st);
+        if (d.mixed) launch_pair_kernels<StokesTNOp<float>, float>(P, a, st, 1, 16 | 1, true);
+        else launch_pair_kernels<StokesTNOp<double>, double>(P, a, st, 1, 16 | 1, false);
     } else {
-        ProfScope prof(prof_variant(1, d.mixed, code), (double)P.n * (double)P.n, st);
-#define SDBIE_STO(T, DL, SL, SUB, SLIP) launch_pair_kernels<StokesOp<T, DL, SL, SUB, SLIP>, T>(a, st)
+#define SDBIE_STO(T, DL, SL, SUB, SLIP) \
+    launch_pair_kernels<StokesOp<T, DL, SL, SUB, SLIP>, T>(P, a, st, 1, code, d.mixed)
         if (!d.mixed) {
             switch (code) {
                 case 1: SDBIE_STO(double, true, false, false, false); break;
@@ -795,15 +869,14 @@ void launch_grad_pass(const Plan& P, const GradDesc& g, hipStream_t st) {
     a.g_K = g.K;
     const unsigned eb = (unsigned)((P.n + 255) / 256);
     {
-        ProfScope prof(prof_variant(2, false, 0), 2.0 * (double)P.n * (double)P.n, st);
         // node as target: A_m = sum_j g_mj
-        launch_pair_kernels<GradOp<false>, double>(a, st);
+        launch_pair_kernels<GradOp<false>, double>(P, a, st, 2, 0, false);
         hipLaunchKernelGGL((epilogue<3>), dim3(eb), dim3(256), 0, st, P.n, 2 * S, (const double*)P.partial,
                            (const double*)nullptr, (const double*)nullptr, 0.0, (const double*)nullptr, 0.0,
                            (const double*)P.nrm, 0.0, 0.0, 0.0, g.out, (const int32_t*)nullptr);
         SDBIE_LAUNCHED();
         // node as source: out = sum_i g_im - A_m
-        launch_pair_kernels<GradOp<true>, double>(a, st);
+        launch_pair_kernels<GradOp<true>, double>(P, a, st, 2, 16, false);
     }
     hipLaunchKernelGGL((epilogue<3>), dim3(eb), dim3(256), 0, st, P.n, 2 * S, (const double*)P.partial,
                        (const double*)nullptr, (const double*)g.out, -1.0, (const double*)nullptr, 0.0,

@@ -28,26 +28,46 @@ std::vector<Rec> g_recs;
 
 }  // namespace
 
-// variant = family * 64 + mixed * 32 + code
-int prof_variant(int family, bool mixed, int code) { return family * 64 + (mixed ? 32 : 0) + code; }
+// variant = ((family * 4 + part) * 2 + mixed) * 32 + code
+// family: 0 Laplace, 1 Stokes, 2 position gradient; part: 0 far kernel,
+// 1 near kernel, 2 source-record packing; code: DL 1, SL 2, SUB 4, SLIP 8,
+// transposed (target normal) 16.
+int prof_variant(int family, bool mixed, int code, int part) {
+    return ((family * 4 + part) * 2 + (mixed ? 1 : 0)) * 32 + code;
+}
+
+namespace {
+void decode(int v, int& family, int& part, int& mixed, int& code) {
+    code = v & 31;
+    mixed = (v >> 5) & 1;
+    part = (v >> 6) & 3;
+    family = v >> 8;
+}
+}  // namespace
 
 std::string prof_name(int v) {
-    const int family = v / 64, mixed = (v / 32) & 1, code = v & 31;
-    if (family == 2) return "position_gradient<f64>";
-    std::string s = family == 0 ? "laplace_pairs<" : "stokes_pairs<";
-    if (code & 16) s = family == 0 ? "laplace_pairs_T<" : "stokes_pairs_T<";
-    s += mixed ? "f32" : "f64";
-    if (code & 1) s += ",DL";
-    if (code & 2) s += ",SL";
-    if (code & 4) s += ",SUB";
-    if (code & 8) s += ",SLIP";
+    int family, part, mixed, code;
+    decode(v, family, part, mixed, code);
+    static const char* parts[] = {"far", "near", "pack", "?"};
+    std::string s = family == 0 ? "laplace" : family == 1 ? "stokes" : "position_gradient";
+    if (code & 16) s += "_T";
+    s += std::string("_") + parts[part] + "<" + (mixed ? "f32" : "f64");
+    if (family < 2) {
+        if (code & 1) s += ",DL";
+        if (code & 2) s += ",SL";
+        if (code & 4) s += ",SUB";
+        if (code & 8) s += ",SLIP";
+    }
     return s + ">";
 }
 
+// Algorithmic flops of one pair in its far-field form (the near kernel's
+// smoothing branch is not counted); 0 for the packing kernel.
 double flops_per_pair(int v) {
-    const int family = v / 64, code = v & 31;
+    int family, part, mixed, code;
+    decode(v, family, part, mixed, code);
     const bool dl = code & 1, sl = code & 2, sub = code & 4;
-    if (family == 2) return 0.0;  // not counted
+    if (family == 2 || part == 2) return 0.0;  // gradient: not counted
     if (code & 16) return family == 0 ? 9.0 + 2 + 5 + 3 : 9.0 + 2 + 5 + 5 + 2 + 6;
     // common: D (3), r^2 (1 mul + 2 fma = 5), rsqrt (1)
     double f = 9.0;

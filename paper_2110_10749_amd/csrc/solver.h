@@ -46,7 +46,7 @@ enum : int {
     kScalMean = 2,
     kScalNorm = 3,
     kScalDrag = 4,   // 3 slots
-    kScalStage = 16, // staging: finite flag (16), bounding box (18..23), weight sum (24)
+    kScalStage = 16, // staging: finite flag (16), bounding box (18..23), weight sum (24), near-pair counts (26, 27)
     kScalGmres = 32, // inner and outer Hessenberg columns / coefficients
 };
 
@@ -60,6 +60,7 @@ struct GmresWS {
 
 struct GmresOut {
     int iters = 0;
+    int checks = 0;  // double-pair true residuals after cycles with float-pair products
     double relres = 0.0;
     bool conv = false;
 };
@@ -88,8 +89,11 @@ struct Ctx {
     void single_layer_laplace(const double* g, double scale, double* out, bool mixed);
     void single_layer_stokes(const double* f, double mu, double scale, const double* add, double* out, bool mixed);
 
-    GmresOut gmres(const GmresWS& ws, const std::function<void(const double*, double*)>& op, const double* b,
-                   double* x, int64_t L, bool x_nonzero, double tol, int restart, int maxit);
+    // operator with a precision flag (true: float pairs)
+    using GmresOp = std::function<void(const double*, double*, bool)>;
+    static constexpr double kAllFloat = __builtin_huge_val();
+    GmresOut gmres(const GmresWS& ws, const GmresOp& op, const double* b, double* x, int64_t L, bool x_nonzero,
+                   double tol, int restart, int maxit, double relax = 0.0);
     void solve(const std::function<void(const double*, double*, bool)>& op, const double* b, double* x, int64_t L,
                bool x_nonzero, double* rbuf, double* cbuf);
 

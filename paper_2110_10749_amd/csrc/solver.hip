@@ -117,8 +117,14 @@ void Ctx::single_layer_stokes(const double* f, double mu, double scale, const do
 // ------------------------------------------------------------------------------
 // GMRES
 // ------------------------------------------------------------------------------
-GmresOut Ctx::gmres(const GmresWS& ws, const std::function<void(const double*, double*)>& op, const double* b,
-                    double* x, int64_t L, bool x_nonzero, double tol, int restart, int maxit) {
+// The operator takes a precision flag (true: float pairs).  relax = 0: every
+// product in double pairs; relax = inf: every product in float pairs; else
+// the Arnoldi products switch to float pairs once the residual estimate is
+// at or below relax * ||b|| (relaxed inexact Krylov: the product error may
+// grow as the residual shrinks), and a cycle that used float pairs ends with
+// a double-pair true residual, which alone decides convergence.
+GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, double* x, int64_t L, bool x_nonzero,
+                    double tol, int restart, int maxit, double relax) {
     GmresOut res;
     const double bnorm = norm(b, L);
     if (bnorm == 0.0) {
@@ -128,8 +134,9 @@ GmresOut Ctx::gmres(const GmresWS& ws, const std::function<void(const double*, d
     }
     double* r = ws.r;
     double* w = ws.w;
+    const bool all32 = std::isinf(relax);
     if (x_nonzero) {
-        op(x, r);
+        op(x, r, all32);
         dev_axpby(1.0, b, -1.0, r, r, L, s);
     } else {
         dev_fill(0.0, x, L, s);
@@ -146,9 +153,12 @@ GmresOut Ctx::gmres(const GmresWS& ws, const std::function<void(const double*, d
         e[0] = beta;
         dev_scale(1.0 / beta, r, ws.V, L, s);
         int k_used = 0;
+        bool cycle32 = false;
         for (int k = 0; k < m; ++k) {
             double* vk = ws.V + (int64_t)k * L;
-            op(vk, w);
+            const bool m32 = all32 || res.relres <= relax;
+            cycle32 = cycle32 || m32;
+            op(vk, w, m32);
             res.iters++;
             double* h1 = ws.dcol;
             double* h2 = ws.dcol + (k + 1);
@@ -190,12 +200,14 @@ GmresOut Ctx::gmres(const GmresWS& ws, const std::function<void(const double*, d
         }
         SDBIE_HIP(hipMemcpyAsync(ws.dy, y.data(), k_used * sizeof(double), hipMemcpyHostToDevice, s));
         dev_multi_axpy_add(ws.V, L, k_used, ws.dy, x, L, s);
-        if (res.relres <= tol || res.iters >= maxit) break;
-        // restart from the true residual
-        op(x, r);
+        const bool verify = cycle32 && !all32;
+        if (!verify && (res.relres <= tol || res.iters >= maxit)) break;
+        // restart from (or verify with) the true residual
+        op(x, r, all32);
         dev_axpby(1.0, b, -1.0, r, r, L, s);
         beta = norm(r, L);
         res.relres = beta / bnorm;
+        if (verify) res.checks++;
     }
     res.conv = res.relres <= tol;
     SDBIE_HIP(hipStreamSynchronize(s));
@@ -211,15 +223,18 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op, con
                 int64_t L, bool x_nonzero, double* rbuf, double* cbuf) {
     if (corr) {
         const bool m32 = debug_level() < 10;  // SDBIE_DEBUG >= 10: double-pair corrections (diagnostics)
-        GmresOut g = gmres(inner, [&](const double* in, double* out) { op(in, out, m32); }, b, x, L, x_nonzero,
-                           tol_corr, o.restart, o.maxit_gmres);
+        GmresOut g = gmres(inner, op, b, x, L, x_nonzero, tol_corr, o.restart, o.maxit_gmres,
+                           m32 ? kAllFloat : 0.0);
         info.gmres_iters += g.iters;
         return;
     }
     const bool mixed = o.prec == SDBIE_MIXED;
-    if (!mixed) {
-        GmresOut g = gmres(inner, [&](const double* in, double* out) { op(in, out, false); }, b, x, L, x_nonzero,
-                           o.tol_gmres, o.restart, o.maxit_gmres);
+    if (!mixed || o.mixed_mode == 2) {
+        // double pairs, or relaxed: double pairs until the residual reaches
+        // tol_mixed, float pairs below it, double-pair true residual at the end
+        GmresOut g = gmres(inner, op, b, x, L, x_nonzero, o.tol_gmres, o.restart, o.maxit_gmres,
+                           mixed ? o.tol_mixed : 0.0);
+        if (mixed) info.refine_steps += g.checks;
         info.gmres_iters += g.iters;
         info.relres = g.relres;
         if (!g.conv) converged = false;
@@ -254,8 +269,7 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op, con
         }
         rel = norm(rbuf, L) / bnorm;
         if (rel <= o.tol_gmres || step >= o.refine_max) break;
-        GmresOut g = gmres(inner, [&](const double* in, double* out) { op(in, out, true); }, rbuf, cbuf, L, false,
-                           o.tol_mixed, o.restart, o.maxit_gmres);
+        GmresOut g = gmres(inner, op, rbuf, cbuf, L, false, o.tol_mixed, o.restart, o.maxit_gmres, kAllFloat);
         info.gmres_iters += g.iters;
         if (have_x) {
             dev_axpby(1.0, x, 1.0, cbuf, x, L, s);
@@ -367,7 +381,7 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
     }
     stokes(prm, U, pstk, fx, ul, false, r2);
     dev_normal_component(P, ul, t0, s);
-    auto op = [&](const double* y, double* out) {
+    auto op = [&](const double* y, double* out, bool) {
         darcy(prm, y, pl, false, nullptr, remove_mean);
         const double* ps = pl;
         if (!remove_mean) {
@@ -605,7 +619,8 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
         dev_adj_stokes(P, l, m0, m1, m2, tB, beta != 0.0 ? tC : nullptr, P.scal + kScalCompS, beta, out, s);
     };
     auto solve_T = [&](const std::function<void(const double*, double*)>& op, const double* b, double* x, int64_t L) {
-        GmresOut g = gmres(inner, op, b, x, L, false, o.tol_gmres, o.restart, o.maxit_gmres);
+        GmresOut g = gmres(inner, [&](const double* in, double* out, bool) { op(in, out); }, b, x, L, false,
+                           o.tol_gmres, o.restart, o.maxit_gmres);
         info.gmres_iters += g.iters;
         info.relres = g.relres;
         if (!g.conv) converged = false;
@@ -651,7 +666,7 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
     // t0 = T'(0)
     copy(gu, tE, 3 * n);
     chain(gp, t0);
-    auto opOuter = [&](const double* y, double* out) {
+    auto opOuter = [&](const double* y, double* out, bool) {
         SLT(y, 1.0, tA);                          // S_L^T y
         dev_scalar_normal(P, tA, mu / K, tE, s);  // (mu/K) N^T S_L^T y
         chain(nullptr, x1);

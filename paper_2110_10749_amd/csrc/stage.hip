@@ -145,21 +145,40 @@ __global__ __launch_bounds__(256) void k_tile_boxes(int64_t n, const double* __r
     if (threadIdx.x < 6) boxes[(int64_t)blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// mask[b][t] = 1 when the boxes of tiles b and t are closer than the cutoff
-__global__ void k_near_masks(int nt, const double* __restrict__ boxes, double rc64, double rc32,
-                             uint8_t* __restrict__ m64, uint8_t* __restrict__ m32) {
+// mask[b][t] = 1 when the boxes of tiles b and t are closer than the cutoff.
+// cnt[0], cnt[1] += the (target, source) pairs of real nodes in the near tile
+// pairs of each precision (integer sums: exact in any order).
+__global__ void k_near_masks(int nt, int64_t n, const double* __restrict__ boxes, double rc64, double rc32,
+                             uint8_t* __restrict__ m64, uint8_t* __restrict__ m32,
+                             unsigned long long* __restrict__ cnt) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)nt * nt) return;
-    const int64_t b = idx / nt, t = idx % nt;
-    const double* A = boxes + b * 6;
-    const double* B = boxes + t * 6;
-    double d2 = 0.0;
-    for (int c = 0; c < 3; ++c) {
-        const double gap = fmax(0.0, fmax(A[2 * c] - B[2 * c + 1], B[2 * c] - A[2 * c + 1]));
-        d2 += gap * gap;
+    unsigned long long c64 = 0, c32 = 0;
+    if (idx < (int64_t)nt * nt) {
+        const int64_t b = idx / nt, t = idx % nt;
+        const double* A = boxes + b * 6;
+        const double* B = boxes + t * 6;
+        double d2 = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            const double gap = fmax(0.0, fmax(A[2 * c] - B[2 * c + 1], B[2 * c] - A[2 * c + 1]));
+            d2 += gap * gap;
+        }
+        const bool n64 = d2 < rc64 * rc64, n32 = d2 < rc32 * rc32;
+        m64[idx] = n64 ? 1 : 0;
+        m32[idx] = n32 ? 1 : 0;
+        const int64_t rb = n - b * kTile < kTile ? n - b * kTile : kTile;
+        const int64_t rt = n - t * kTile < kTile ? n - t * kTile : kTile;
+        const unsigned long long pr = (unsigned long long)(rb * rt);
+        c64 = n64 ? pr : 0;
+        c32 = n32 ? pr : 0;
     }
-    m64[idx] = d2 < rc64 * rc64 ? 1 : 0;
-    m32[idx] = d2 < rc32 * rc32 ? 1 : 0;
+    for (int off = 32; off > 0; off >>= 1) {
+        c64 += __shfl_down(c64, off);
+        c32 += __shfl_down(c32, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (c64) atomicAdd(cnt, c64);
+        if (c32) atomicAdd(cnt + 1, c32);
+    }
 }
 
 }  // namespace
@@ -168,14 +187,15 @@ void stage_surface(Plan& P, const sdbie_surface* s, hipStream_t st) {
     const int64_t n = P.n;
     // finite check of the node data first (Morton keys of NaN are meaningless)
     int* flag = reinterpret_cast<int*>(P.scal + kScalStage);
-    SDBIE_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
-    dev_check_finite(s->x, 3 * n, flag, st);
-    dev_check_finite(s->nrm, 3 * n, flag, st);
-    dev_check_finite(s->w, n, flag, st);
-    int hflag = 0;
-    SDBIE_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    SDBIE_HIP(hipMemsetAsync(flag, 0, 2 * sizeof(int), st));
+    dev_check_finite(s->x, 3 * n, kMaxCoord, flag, st);
+    dev_check_finite(s->nrm, 3 * n, HUGE_VAL, flag, st);
+    dev_check_finite(s->w, n, HUGE_VAL, flag, st);
+    int hflag[2] = {0, 0};
+    SDBIE_HIP(hipMemcpyAsync(hflag, flag, sizeof(hflag), hipMemcpyDeviceToHost, st));
     SDBIE_HIP(hipStreamSynchronize(st));
-    if (hflag) throw Error(SDBIE_ERR_NONFINITE, "non-finite node coordinates, normals or weights");
+    if (hflag[0]) throw Error(SDBIE_ERR_NONFINITE, "non-finite node coordinates, normals or weights");
+    if (hflag[1]) throw Error(SDBIE_ERR_ARG, "node coordinates must not exceed 1e15 in magnitude");
 
     double* bb = P.scal + kScalStage + 2;
     hipLaunchKernelGGL(k_bbox, dim3(3), dim3(256), 0, st, n, s->x, bb);
@@ -201,9 +221,16 @@ void stage_surface(Plan& P, const sdbie_surface* s, hipStream_t st) {
     const double rc64 = SDBIE_RHO_CUT_STOKES_F64 * P.delta * (1.0 + 1e-6);
     const double rc32 = SDBIE_RHO_CUT_STOKES_F32 * P.delta * (1.0 + 1e-6);
     const int64_t nt2 = (int64_t)P.ntiles * P.ntiles;
-    hipLaunchKernelGGL(k_near_masks, dim3((unsigned)((nt2 + 255) / 256)), dim3(256), 0, st, P.ntiles,
-                       (const double*)P.boxes, rc64, rc32, P.mask64, P.mask32);
+    unsigned long long* cnt = reinterpret_cast<unsigned long long*>(P.scal + kScalStage + 10);
+    SDBIE_HIP(hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned long long), st));
+    hipLaunchKernelGGL(k_near_masks, dim3((unsigned)((nt2 + 255) / 256)), dim3(256), 0, st, P.ntiles, n,
+                       (const double*)P.boxes, rc64, rc32, P.mask64, P.mask32, cnt);
     SDBIE_LAUNCHED();
+    unsigned long long hc[2] = {0, 0};
+    SDBIE_HIP(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
+    SDBIE_HIP(hipStreamSynchronize(st));
+    P.near_pairs64 = (double)hc[0];
+    P.near_pairs32 = (double)hc[1];
     dev_dot(P, P.w, nullptr, n, P.scal + kScalStage + 8, st);
     P.area = host_read_scalar(P.scal + kScalStage + 8, st);
     if (!(P.area > 0.0)) throw Error(SDBIE_ERR_ARG, "the quadrature weights sum to zero");

@@ -64,6 +64,9 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
     # bad delta
     bad = B.Surface(10, 1, 1, 1, -1.0)
     assert L.sdbie_plan_create(ctypes.byref(h), ctypes.byref(bad), 50, None, 0, None) == B.ERR_ARG
+    for d in (1e-16, 2e15, float("inf"), float("nan")):  # outside [1e-15, 1e15]
+        bad = B.Surface(10, 1, 1, 1, d)
+        assert L.sdbie_plan_create(ctypes.byref(h), ctypes.byref(bad), 50, None, 0, None) == B.ERR_ARG
     # n out of range
     bad = B.Surface(0, 1, 1, 1, 0.1)
     assert L.sdbie_plan_create(ctypes.byref(h), ctypes.byref(bad), 50, None, 0, None) == B.ERR_ARG

@@ -153,6 +153,12 @@ def test_error_paths(sd, s16):
     with pytest.raises(sd.SdbieError) as e:
         sd.Plan(dev(x), dev(S.n), dev(S.w), 0.1)
     assert e.value.code == -2
+    # coordinates beyond 1e15 are rejected (squared distances must stay normal numbers)
+    x = S.x.copy()
+    x[1, 7] = 2e15
+    with pytest.raises(sd.SdbieError) as e:
+        sd.Plan(dev(x), dev(S.n), dev(S.w), 0.1)
+    assert e.value.code == -1
     # outer GMRES with lagged slip is not an affine map of the interface unknown
     with pytest.raises(sd.SdbieError) as e:
         sd.ddm_solve(plan, 1.0, 1.0, 1.0, E, None, opts=dict(outer="gmres", slip="lagged"))
@@ -171,20 +177,19 @@ def test_plans_are_independent_and_reusable(sd):
     assert np.array_equal(r1, r1b)  # deterministic, bitwise
 
 
-@pytest.mark.parametrize("inv_h,K,alpha", [(32, 1.0, 0.1), (32, 1e-2, 1.0), (16, 1e-4, 10.0)])
-def test_mixed_matches_fp64_at_solver_tolerances(sd, inv_h, K, alpha):
+@pytest.mark.parametrize("mode", ["refine", "relaxed"])
+@pytest.mark.parametrize("inv_h,K,alpha", [(32, 1.0, 0.1), (32, 1e-2, 1.0), (16, 1e-4, 0.1)])
+def test_mixed_matches_fp64_at_solver_tolerances(sd, inv_h, K, alpha, mode):
     # default tolerances (local 1e-10, interface 1e-8): the mixed solve (float
-    # pairs, double refinement) lands on the same drag as the FP64 path.
-    # beta = alpha mu / sqrt(K) spans 0.1 .. 1000; at large beta the implicit-slip
-    # Stokes operator behaves like I + beta (smoothing single layer) and needs a
-    # long Krylov space (restart 200)
+    # pairs, double residuals) lands on the same drag as the FP64 path, for
+    # beta = alpha mu / sqrt(K) = 0.1 .. 10 and both mixed schemes
     S = surfaces.sphere(1.0 / inv_h)
-    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / inv_h, max_restart=200)
-    o = dict(restart=200, maxit_gmres=2000)
-    p64, u64, D64, i64 = sd.ddm_solve(plan, 1.0, K, alpha, E, None, opts=dict(prec="fp64", **o))
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / inv_h)
+    p64, u64, D64, i64 = sd.ddm_solve(plan, 1.0, K, alpha, E, None, opts=dict(prec="fp64"))
     print("fp64", D64[2], i64, flush=True)
-    p32, u32, D32, i32 = sd.ddm_solve(plan, 1.0, K, alpha, E, None, opts=dict(prec="mixed", **o))
-    print("mixed", D32[2], i32, flush=True)
+    p32, u32, D32, i32 = sd.ddm_solve(plan, 1.0, K, alpha, E, None, opts=dict(prec="mixed", mixed_mode=mode))
+    print("mixed", mode, D32[2], i32, flush=True)
+    assert i32["applies_mixed"] > 0
     De = exact.bjs_drag(K=K, beta=alpha / math.sqrt(K))
     assert i64["converged"] and i32["converged"]
     assert abs(D32[2] - D64[2]) < 1e-8 * abs(D64[2])
