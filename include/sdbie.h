@@ -107,6 +107,11 @@ typedef struct {
                            D-N corrections); 2 = relaxed GMRES in every local solve (double-pair
                            products until the residual reaches tol_mixed, float pairs after it,
                            convergence decided by a double-pair true residual) */
+    int relax_outer;    /* outer = 1: 1 = inexact interface products (local solves of an interface
+                           GMRES step loosened in proportion to the interface residual reached,
+                           float pairs throughout once loose enough with SDBIE_MIXED; convergence
+                           decided by the true interface residual of full-accuracy final solves);
+                           0 = every local solve to tol_gmres */
 } sdbie_opts;
 
 typedef struct {
@@ -124,7 +129,7 @@ typedef struct sdbie_plan_s* sdbie_plan;
 
 /* Fill `o` with the defaults: tol_gmres 1e-10, tol_ddm 1e-8, theta 0.5,
  * maxit_gmres 500, restart 50, maxit_ddm 200, outer 1, slip 0, prec FP64,
- * tol_mixed 1e-4, refine_max 8, mixed_mode 2. */
+ * tol_mixed 1e-4, refine_max 8, mixed_mode 2, relax_outer 1. */
 void sdbie_default_opts(sdbie_opts* o);
 
 /* Bytes of device workspace a plan for n nodes (1 <= n <= 2^23) and GMRES

@@ -44,7 +44,8 @@ class Opts(ctypes.Structure):
     _fields_ = [("tol_gmres", ctypes.c_double), ("tol_ddm", ctypes.c_double), ("theta", ctypes.c_double),
                 ("maxit_gmres", ctypes.c_int), ("restart", ctypes.c_int), ("maxit_ddm", ctypes.c_int),
                 ("outer", ctypes.c_int), ("slip", ctypes.c_int), ("prec", ctypes.c_int),
-                ("tol_mixed", ctypes.c_double), ("refine_max", ctypes.c_int), ("mixed_mode", ctypes.c_int)]
+                ("tol_mixed", ctypes.c_double), ("refine_max", ctypes.c_int), ("mixed_mode", ctypes.c_int),
+                ("relax_outer", ctypes.c_int)]
 
 
 class KernelStat(ctypes.Structure):
@@ -64,6 +65,7 @@ class Info(ctypes.Structure):
 
 
 _lib = None
+ABI_VERSION = 2  # layout of the structs above (sdbie_abi_version)
 
 
 def lib():
@@ -106,6 +108,9 @@ def lib():
         L.sdbie_profile_enable.restype = i32
         L.sdbie_profile_read.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
         L.sdbie_profile_read.restype = i32
+        if L.sdbie_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI {L.sdbie_abi_version()}, this binding needs {ABI_VERSION}: "
+                              f"rebuild it")
         _lib = L
     return _lib
 

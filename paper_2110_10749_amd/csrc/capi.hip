@@ -23,7 +23,7 @@ int64_t next_pow2(int64_t n) {
 }
 
 struct Layout {
-    size_t x, nrm, w, wn, px, pn, pw, px32, boxes, mask64, mask32, perm, keys, partial, rec, red, scal, vecs,
+    size_t x, nrm, w, wn, px, pn, pw, px32, boxes, uboxes, mask64, mask32, perm, keys, partial, rec, red, scal, vecs,
         basis_in, basis_out, total;
 };
 
@@ -46,6 +46,7 @@ Layout layout(int64_t n, int m) {
     L.pw = take(npad * d);
     L.px32 = take(3 * npad * f);
     L.boxes = take(nt * 6 * d);
+    L.uboxes = take(npad / kNearUnit * 6 * d);
     L.mask64 = take(nt * nt);
     L.mask32 = take(nt * nt);
     L.perm = take(n * sizeof(int32_t));
@@ -95,6 +96,7 @@ sdbie_opts checked_opts(const sdbie_opts* op, const Plan& P) {
     if (!(o.tol_mixed > 0.0 && o.tol_mixed < 1.0)) fail(SDBIE_ERR_ARG, "tol_mixed must lie in (0, 1)");
     if (o.refine_max < 1) fail(SDBIE_ERR_ARG, "refine_max must be >= 1");
     if (o.mixed_mode < 0 || o.mixed_mode > 2) fail(SDBIE_ERR_ARG, "mixed_mode must be 0, 1 or 2");
+    if (o.relax_outer != 0 && o.relax_outer != 1) fail(SDBIE_ERR_ARG, "relax_outer must be 0 or 1");
     return o;
 }
 
@@ -139,6 +141,7 @@ void carve_workspace(Plan& P, void* ws) {
     P.pw = reinterpret_cast<double*>(b + L.pw);
     P.px32 = reinterpret_cast<float*>(b + L.px32);
     P.boxes = reinterpret_cast<double*>(b + L.boxes);
+    P.uboxes = reinterpret_cast<double*>(b + L.uboxes);
     P.mask64 = reinterpret_cast<uint8_t*>(b + L.mask64);
     P.mask32 = reinterpret_cast<uint8_t*>(b + L.mask32);
     P.perm = reinterpret_cast<int32_t*>(b + L.perm);
@@ -173,6 +176,7 @@ void sdbie_default_opts(sdbie_opts* o) {
     o->tol_mixed = 1e-4;
     o->refine_max = 8;
     o->mixed_mode = 2;
+    o->relax_outer = 1;
 }
 
 size_t sdbie_workspace_bytes(int64_t n, int max_restart) {
@@ -180,7 +184,7 @@ size_t sdbie_workspace_bytes(int64_t n, int max_restart) {
     return workspace_bytes(n, max_restart);
 }
 
-int sdbie_abi_version(void) { return 1; }
+int sdbie_abi_version(void) { return 2; }
 
 const char* sdbie_last_error(void) { return g_last_error.c_str(); }
 

@@ -99,6 +99,7 @@ struct Plan {
     double* pw = nullptr;   // [npad]
     float* px32 = nullptr;  // [3][npad]
     double* boxes = nullptr;   // [ntiles][6] min/max per axis
+    double* uboxes = nullptr;  // [npad / kNearUnit][6]: the same per near-field unit of sources
     uint8_t* mask64 = nullptr; // [ntiles][ntiles]: 1 if the tile pair may hold a pair with rho < double cutoff
     uint8_t* mask32 = nullptr; // [ntiles][ntiles]: same with the float cutoff
     int32_t* perm = nullptr;  // sorted index -> caller index

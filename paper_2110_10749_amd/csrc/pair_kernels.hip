@@ -124,6 +124,8 @@ struct KArgs {
     double c_dl, c_sl, slip_beta;
     double inv_delta;
     double rc2;         // (rho_cut * delta)^2
+    double rcu2;        // (rho_cut * delta)^2 with the tile masks' relative margin (unit box test)
+    const double* uboxes;  // [npad / kNearUnit][6] source unit boxes
     double* partial;    // [2 nsplit][C][n]
     void* rec;          // source records of the pass [npad][Op::R] (T)
     int unit_w;         // sources enter with weight 1 (transposed single layers)
@@ -636,19 +638,37 @@ __global__ __launch_bounds__(kTPB) void far_pairs(KArgs a) {
 }
 
 // Near-field pass: the tiles of the target tile's mask row, cut into units of
-// kNearUnit sources dealt round-robin to the splits; every pair takes the
-// smoothing branch when r < rho_cut delta.
+// kNearUnit sources dealt round-robin to the splits.  A (wave, unit) pair
+// whose boxes are at least the cutoff apart (and which holds no padding node)
+// runs the plain far-field body; every other pair takes the smoothing branch
+// when r < rho_cut delta.
 template <class Op, typename T>
 __global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
     // the double smoothing branch is long: one record per step keeps its registers in bounds
     constexpr int NU = sizeof(T) == 8 ? 1 : Op::U;
-    static_assert(kNearUnit % NU == 0, "unroll must divide the near unit");
+    // far units: half the far kernel's unroll (the near kernel holds more scalars)
+    constexpr int FU = Op::U > 1 ? Op::U / 2 : 1;
+    static_assert(kNearUnit % NU == 0 && kNearUnit % FU == 0, "unroll must divide the near unit");
+    static_assert(kNearUnit == 64, "one wave of targets per unit test");
     const int split = blockIdx.x % a.nsplit;
     const int b = blockIdx.x / a.nsplit;
     const int64_t i = (int64_t)b * kTPB + threadIdx.x;
     Op op;
     op.init(a, i);
     const T id = T(a.inv_delta), id2 = id * id, rc2 = T(a.rc2);
+    // bounding box of the wave's 64 targets (equal in every lane)
+    const int64_t w0 = (int64_t)b * kTPB + (threadIdx.x & ~63);
+    const bool wave_full = w0 + 64 <= a.n;
+    double wb[6];
+    for (int c = 0; c < 3; ++c) {
+        double lo = a.x[c * a.npad + i], hi = lo;
+        for (int off = 32; off > 0; off >>= 1) {
+            lo = fmin(lo, __shfl_xor(lo, off));
+            hi = fmax(hi, __shfl_xor(hi, off));
+        }
+        wb[2 * c] = lo;
+        wb[2 * c + 1] = hi;
+    }
     const uint8_t* row = a.mask + (int64_t)b * a.ntiles;
     const T* rec = static_cast<const T*>(a.rec);
     constexpr int kUnits = kTile / kNearUnit;
@@ -662,10 +682,27 @@ __global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
             bal &= bal - 1;
             for (int q = 0; q < kUnits; ++q) {
                 if ((rank * kUnits + q) % a.nsplit != split) continue;
-                const T* ru = rec + ((int64_t)t * kTile + q * kNearUnit) * Op::R;
+                const int64_t u0 = (int64_t)t * kTile + q * kNearUnit;
+                const T* ru = rec + u0 * Op::R;
+                bool far_unit = wave_full && u0 + kNearUnit <= a.n;
+                if (far_unit) {
+                    const double* ub = a.uboxes + (u0 / kNearUnit) * 6;
+                    double d2 = 0.0;
+                    for (int c = 0; c < 3; ++c) {
+                        const double gap = fmax(0.0, fmax(wb[2 * c] - ub[2 * c + 1], ub[2 * c] - wb[2 * c + 1]));
+                        d2 += gap * gap;
+                    }
+                    far_unit = d2 >= a.rcu2;
+                }
+                if (far_unit) {
 #pragma unroll 1
-                for (int jj = 0; jj < kNearUnit; jj += NU)
-                    pair_group<Op, T, true, NU>(op, ru + jj * Op::R, id, id2, rc2);
+                    for (int jj = 0; jj < kNearUnit; jj += FU)
+                        pair_group<Op, T, false, FU>(op, ru + jj * Op::R, id, id2, rc2);
+                } else {
+#pragma unroll 1
+                    for (int jj = 0; jj < kNearUnit; jj += NU)
+                        pair_group<Op, T, true, NU>(op, ru + jj * Op::R, id, id2, rc2);
+                }
                 op.flush();
             }
             ++rank;
@@ -718,6 +755,8 @@ KArgs make_args(const Plan& P, const PassDesc& d, int nsplit, double cut) {
     a.slip_beta = d.slip_beta;
     a.inv_delta = 1.0 / P.delta;
     a.rc2 = (cut * P.delta) * (cut * P.delta);
+    a.rcu2 = (cut * P.delta * (1.0 + 1e-6)) * (cut * P.delta * (1.0 + 1e-6));
+    a.uboxes = P.uboxes;
     a.partial = P.partial;
     a.rec = P.rec;
     a.unit_w = d.unit_src_weight ? 1 : 0;

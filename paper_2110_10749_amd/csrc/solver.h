@@ -76,6 +76,10 @@ struct Ctx {
     // local solves by plain GMRES to tol_corr
     bool corr = false;
     double tol_corr = 0.0;
+    // inexact interface products: local solves to tol_local (0: tol_gmres);
+    // loose32: every pass of the local solves (right-hand sides included) in float pairs
+    double tol_local = 0.0;
+    bool loose32 = false;
 
     Ctx(Plan& plan, hipStream_t st, const sdbie_opts& opts);
     void finish();
@@ -89,8 +93,10 @@ struct Ctx {
     void single_layer_laplace(const double* g, double scale, double* out, bool mixed);
     void single_layer_stokes(const double* f, double mu, double scale, const double* add, double* out, bool mixed);
 
-    // operator with a precision flag (true: float pairs)
-    using GmresOp = std::function<void(const double*, double*, bool)>;
+    // operator with a precision flag (true: float pairs) and the relative
+    // residual estimate of the iteration the product belongs to (0 for true
+    // residuals, which need full accuracy)
+    using GmresOp = std::function<void(const double*, double*, bool, double)>;
     static constexpr double kAllFloat = __builtin_huge_val();
     GmresOut gmres(const GmresWS& ws, const GmresOp& op, const double* b, double* x, int64_t L, bool x_nonzero,
                    double tol, int restart, int maxit, double relax = 0.0);

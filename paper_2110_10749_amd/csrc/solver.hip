@@ -136,7 +136,7 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
     double* w = ws.w;
     const bool all32 = std::isinf(relax);
     if (x_nonzero) {
-        op(x, r, all32);
+        op(x, r, all32, 0.0);
         dev_axpby(1.0, b, -1.0, r, r, L, s);
     } else {
         dev_fill(0.0, x, L, s);
@@ -158,7 +158,7 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
             double* vk = ws.V + (int64_t)k * L;
             const bool m32 = all32 || res.relres <= relax;
             cycle32 = cycle32 || m32;
-            op(vk, w, m32);
+            op(vk, w, m32, res.relres);
             res.iters++;
             double* h1 = ws.dcol;
             double* h2 = ws.dcol + (k + 1);
@@ -203,7 +203,7 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
         const bool verify = cycle32 && !all32;
         if (!verify && (res.relres <= tol || res.iters >= maxit)) break;
         // restart from (or verify with) the true residual
-        op(x, r, all32);
+        op(x, r, all32, 0.0);
         dev_axpby(1.0, b, -1.0, r, r, L, s);
         beta = norm(r, L);
         res.relres = beta / bnorm;
@@ -219,8 +219,9 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
 
 // Solve A x = b: plain GMRES with the double-pair operator, or iterative
 // refinement (double residual, float-pair correction solves).
-void Ctx::solve(const std::function<void(const double*, double*, bool)>& op, const double* b, double* x,
+void Ctx::solve(const std::function<void(const double*, double*, bool)>& op3, const double* b, double* x,
                 int64_t L, bool x_nonzero, double* rbuf, double* cbuf) {
+    const GmresOp op = [&](const double* in, double* out, bool m32, double) { op3(in, out, m32); };
     if (corr) {
         const bool m32 = debug_level() < 10;  // SDBIE_DEBUG >= 10: double-pair corrections (diagnostics)
         GmresOut g = gmres(inner, op, b, x, L, x_nonzero, tol_corr, o.restart, o.maxit_gmres,
@@ -228,11 +229,18 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op, con
         info.gmres_iters += g.iters;
         return;
     }
+    const double tol = tol_local > 0.0 ? tol_local : o.tol_gmres;
+    if (loose32) {
+        // a loose inexact interface product: float pairs throughout, no double check
+        GmresOut g = gmres(inner, op, b, x, L, x_nonzero, tol, o.restart, o.maxit_gmres, kAllFloat);
+        info.gmres_iters += g.iters;
+        return;
+    }
     const bool mixed = o.prec == SDBIE_MIXED;
     if (!mixed || o.mixed_mode == 2) {
         // double pairs, or relaxed: double pairs until the residual reaches
         // tol_mixed, float pairs below it, double-pair true residual at the end
-        GmresOut g = gmres(inner, op, b, x, L, x_nonzero, o.tol_gmres, o.restart, o.maxit_gmres,
+        GmresOut g = gmres(inner, op, b, x, L, x_nonzero, tol, o.restart, o.maxit_gmres,
                            mixed ? o.tol_mixed : 0.0);
         if (mixed) info.refine_steps += g.checks;
         info.gmres_iters += g.iters;
@@ -262,13 +270,13 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op, con
             break;
         }
         if (have_x) {
-            op(x, rbuf, false);
+            op3(x, rbuf, false);
             dev_axpby(1.0, b, -1.0, rbuf, rbuf, L, s);
         } else {
             copy(b, rbuf, L);
         }
         rel = norm(rbuf, L) / bnorm;
-        if (rel <= o.tol_gmres || step >= o.refine_max) break;
+        if (rel <= tol || step >= o.refine_max) break;
         GmresOut g = gmres(inner, op, rbuf, cbuf, L, false, o.tol_mixed, o.restart, o.maxit_gmres, kAllFloat);
         info.gmres_iters += g.iters;
         if (have_x) {
@@ -278,11 +286,11 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op, con
             have_x = true;
         }
         const double bound = 2.0 * rel * (g.relres + 5e-6);
-        if (g.conv && bound <= o.tol_gmres) predicted = bound;
+        if (g.conv && bound <= tol) predicted = bound;
     }
     info.refine_steps += step;
     info.relres = rel;
-    if (rel > o.tol_gmres) converged = false;
+    if (rel > tol) converged = false;
 }
 
 // ------------------------------------------------------------------------------
@@ -293,7 +301,7 @@ void Ctx::darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonz
     const int64_t n = P.n;
     double* b = P.vec(kVecDarcyB);
     // b = -S_L[g], g = dp/dn = -(mu/K) v   =>  b = (mu/K) S_L[v]
-    single_layer_laplace(v, prm.mu / prm.K, b, corr && debug_level() < 10);
+    single_layer_laplace(v, prm.mu / prm.K, b, (corr && debug_level() < 10) || loose32);
     if (extra_rhs) dev_axpby(1.0, b, 1.0, extra_rhs, b, n, s);
     solve([&](const double* in, double* out, bool mx) { op_darcy(in, out, mx); }, b, p, n, p_nonzero,
           P.vec(kVecRefR), P.vec(kVecRefC));
@@ -312,7 +320,7 @@ void Ctx::stokes(const sdbie_params& prm, const double U[3], const double* p, co
     const bool lagged = o.slip == 1 && beta != 0.0;
     // traction without the implicit slip term (lagged slip uses the entry u)
     dev_traction(P, p, lagged ? u : nullptr, lagged ? beta : 0.0, fx, f, s);
-    single_layer_stokes(f, prm.mu, -1.0, U, rhs, corr && debug_level() < 10);
+    single_layer_stokes(f, prm.mu, -1.0, U, rhs, (corr && debug_level() < 10) || loose32);
     if (extra_rhs) dev_axpby(1.0, rhs, 1.0, extra_rhs, rhs, 3 * n, s);
     const double b_impl = lagged ? 0.0 : beta;
     solve([&](const double* in, double* out, bool mx) { op_stokes(in, out, prm.mu, b_impl, mx); }, rhs, u, 3 * n,
@@ -358,6 +366,22 @@ void Ctx::ddm(const sdbie_params& prm, const double U[3], const double* fx, doub
 // (I - T_lin) v = T(0) and finish with one more Darcy and Stokes solve.
 // r1, r2 (nullable) are extra right-hand sides of the Darcy and Stokes
 // equations (used by the coupled refinement).
+//
+// Inexact products (relax_outer, not in the coupled refinement): a Krylov
+// product taken when the interface residual estimate is rr ||T(0)|| only needs
+// an error of order tol ||T(0)|| / rr, so its local solves run to
+// clamp(kOuterSafety tol / rr, tol_gmres, kOuterLoosest), and with float
+// pairs throughout once that is at least kLooseFloat.  The final solves are
+// full-accuracy; their u.n - v is the true interface residual, and a cycle
+// on the correction equation (I - T_lin) d = u.n - v follows when it is
+// above tol.
+namespace {
+constexpr double kOuterSafety = 1e-3;
+constexpr double kOuterLoosest = 1e-2;
+constexpr double kLooseFloat = 1e-5;  // float-pair operator error is ~1e-7 relative
+constexpr int kOuterCycles = 4;
+}  // namespace
+
 void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx, const double* r1, const double* r2,
                     double* p, double* u, bool remove_mean, double tol) {
     const int64_t n = P.n;
@@ -367,6 +391,8 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
     double* pl = P.vec(kVecPl);
     double* ul = P.vec(kVecUl);
     double* pp = P.vec(kVecCoupledV);
+    double* dv = P.vec(kVecVn);
+    const bool relax = o.relax_outer != 0 && !corr;
     // t0 = T(0)
     if (r1) {
         dev_fill(0.0, v, n, s);
@@ -381,7 +407,16 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
     }
     stokes(prm, U, pstk, fx, ul, false, r2);
     dev_normal_component(P, ul, t0, s);
-    auto op = [&](const double* y, double* out, bool) {
+    const double t0n = relax ? norm(t0, n) : 0.0;
+    double tol_cyc = tol;  // relative tolerance of the current cycle
+    auto op = [&](const double* y, double* out, bool, double rr) {
+        const double tl_save = tol_local;
+        const bool l_save = loose32;
+        if (relax && rr > 0.0) {
+            const double tl = std::min(kOuterLoosest, std::max(o.tol_gmres, kOuterSafety * tol_cyc / rr));
+            tol_local = tl;
+            loose32 = o.prec == SDBIE_MIXED && tl >= kLooseFloat;
+        }
         darcy(prm, y, pl, false, nullptr, remove_mean);
         const double* ps = pl;
         if (!remove_mean) {
@@ -391,18 +426,40 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
         stokes(prm, zero, ps, nullptr, ul, false, nullptr);
         dev_normal_component(P, ul, out, s);
         dev_axpby(1.0, y, -1.0, out, out, n, s);
+        tol_local = tl_save;
+        loose32 = l_save;
+    };
+    auto finish = [&]() {
+        darcy(prm, v, p, false, r1, remove_mean);
+        const double* ps = p;
+        if (!remove_mean) {
+            project_mean(p, pp);
+            ps = pp;
+        }
+        stokes(prm, U, ps, fx, u, false, r2);
     };
     GmresOut g = gmres(outer, op, t0, v, n, false, tol, o.restart, o.maxit_ddm);
     info.ddm_iters += g.iters;
     info.ddm_res = g.relres;
-    if (!g.conv && !corr) converged = false;
-    darcy(prm, v, p, false, r1, remove_mean);
-    const double* ps = p;
-    if (!remove_mean) {
-        project_mean(p, pp);
-        ps = pp;
+    bool conv = g.conv;
+    finish();
+    for (int cyc = 1; relax && t0n > 0.0; ++cyc) {
+        // true interface residual T(v) - v = u.n - v
+        dev_normal_component(P, u, pl, s);
+        dev_axpby(1.0, pl, -1.0, v, pl, n, s);
+        const double rt = norm(pl, n) / t0n;
+        info.ddm_res = rt;
+        conv = rt <= tol;
+        if (conv || cyc >= kOuterCycles || info.ddm_iters >= o.maxit_ddm) break;
+        // correction cycle: (I - T_lin) d = u.n - v, relative tolerance tol / rt
+        copy(pl, t0, n);
+        tol_cyc = std::min(0.5, tol / rt);
+        GmresOut gc = gmres(outer, op, t0, dv, n, false, tol_cyc, o.restart, o.maxit_ddm - info.ddm_iters);
+        info.ddm_iters += gc.iters;
+        dev_axpby(1.0, v, 1.0, dv, v, n, s);
+        finish();
     }
-    stokes(prm, U, ps, fx, u, false, r2);
+    if (!conv && !corr) converged = false;
 }
 
 // out = p - (sum_j w_j p_j / |S|)
@@ -619,8 +676,8 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
         dev_adj_stokes(P, l, m0, m1, m2, tB, beta != 0.0 ? tC : nullptr, P.scal + kScalCompS, beta, out, s);
     };
     auto solve_T = [&](const std::function<void(const double*, double*)>& op, const double* b, double* x, int64_t L) {
-        GmresOut g = gmres(inner, [&](const double* in, double* out, bool) { op(in, out); }, b, x, L, false,
-                           o.tol_gmres, o.restart, o.maxit_gmres);
+        GmresOut g = gmres(inner, [&](const double* in, double* out, bool, double) { op(in, out); }, b, x, L,
+                           false, o.tol_gmres, o.restart, o.maxit_gmres);
         info.gmres_iters += g.iters;
         info.relres = g.relres;
         if (!g.conv) converged = false;
@@ -666,7 +723,7 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
     // t0 = T'(0)
     copy(gu, tE, 3 * n);
     chain(gp, t0);
-    auto opOuter = [&](const double* y, double* out, bool) {
+    auto opOuter = [&](const double* y, double* out, bool, double) {
         SLT(y, 1.0, tA);                          // S_L^T y
         dev_scalar_normal(P, tA, mu / K, tE, s);  // (mu/K) N^T S_L^T y
         chain(nullptr, x1);

@@ -123,18 +123,19 @@ __global__ void k_pad(int64_t n, int64_t npad, const double* __restrict__ xs, co
     pw[k] = k < n ? ws[k] : 0.0;
 }
 
-// bounding box of each tile of kTile consecutive (sorted) real nodes
-__global__ __launch_bounds__(256) void k_tile_boxes(int64_t n, const double* __restrict__ xs,
-                                                     double* __restrict__ boxes) {
-    __shared__ double sh[6][256];
-    const int64_t k = (int64_t)blockIdx.x * kTile + threadIdx.x;
+// bounding box of each group of W consecutive (sorted) real nodes (empty:
+// +inf / -inf for a group of padding only); one block of W threads per group
+template <int W>
+__global__ __launch_bounds__(W) void k_boxes(int64_t n, const double* __restrict__ xs, double* __restrict__ boxes) {
+    __shared__ double sh[6][W];
+    const int64_t k = (int64_t)blockIdx.x * W + threadIdx.x;
     for (int c = 0; c < 3; ++c) {
         const double v = k < n ? xs[c * n + k] : NAN;
         sh[2 * c][threadIdx.x] = k < n ? v : INFINITY;
         sh[2 * c + 1][threadIdx.x] = k < n ? v : -INFINITY;
     }
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = W / 2; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s)
             for (int c = 0; c < 3; ++c) {
                 sh[2 * c][threadIdx.x] = fmin(sh[2 * c][threadIdx.x], sh[2 * c][threadIdx.x + s]);
@@ -215,7 +216,11 @@ void stage_surface(Plan& P, const sdbie_surface* s, hipStream_t st) {
                        (const double*)P.x, (const double*)P.nrm, (const double*)P.w, (const double*)bb, P.px, P.pn,
                        P.pw, P.px32);
     SDBIE_LAUNCHED();
-    hipLaunchKernelGGL(k_tile_boxes, dim3((unsigned)P.ntiles), dim3(kTile), 0, st, n, (const double*)P.x, P.boxes);
+    hipLaunchKernelGGL((k_boxes<kTile>), dim3((unsigned)P.ntiles), dim3(kTile), 0, st, n, (const double*)P.x,
+                       P.boxes);
+    SDBIE_LAUNCHED();
+    hipLaunchKernelGGL((k_boxes<kNearUnit>), dim3((unsigned)(P.npad / kNearUnit)), dim3(kNearUnit), 0, st, n,
+                       (const double*)P.x, P.uboxes);
     SDBIE_LAUNCHED();
     // cutoffs with a relative margin of 1e-6 (the far kernels assume rho >= rho_cut)
     const double rc64 = SDBIE_RHO_CUT_STOKES_F64 * P.delta * (1.0 + 1e-6);
