@@ -48,7 +48,9 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ 
     if (threadIdx.x == 0) out[j] = r;
 }
 
-// part[b][j] = sum over block b's chunk of V_j . w
+// part[b][j] = sum over block b's chunk of V_j . w; blockIdx.y takes kDotCols
+// columns at a time, so w is read once per kDotCols columns (fixed order)
+constexpr int kDotCols = 8;
 __global__ __launch_bounds__(256) void k_multidot_partial(const double* __restrict__ V, int64_t ld, int k,
                                                           const double* __restrict__ w, int64_t len,
                                                           double* __restrict__ part) {
@@ -56,12 +58,20 @@ __global__ __launch_bounds__(256) void k_multidot_partial(const double* __restri
     const int64_t chunk = (len + gridDim.x - 1) / gridDim.x;
     const int64_t lo = (int64_t)blockIdx.x * chunk;
     const int64_t hi = lo + chunk < len ? lo + chunk : len;
-    for (int j = 0; j < k; ++j) {
-        const double* v = V + (int64_t)j * ld;
-        double s = 0.0;
-        for (int64_t i = lo + threadIdx.x; i < hi; i += 256) s += v[i] * w[i];
-        const double r = block_sum(s, sh);
-        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * k + j] = r;
+    const int j0 = blockIdx.y * kDotCols;
+    const int nc = k - j0 < kDotCols ? k - j0 : kDotCols;
+    double acc[kDotCols];
+#pragma unroll
+    for (int c = 0; c < kDotCols; ++c) acc[c] = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) {
+        const double wi = w[i];
+#pragma unroll
+        for (int c = 0; c < kDotCols; ++c)
+            if (c < nc) acc[c] += V[(int64_t)(j0 + c) * ld + i] * wi;
+    }
+    for (int c = 0; c < nc; ++c) {
+        const double r = block_sum(acc[c], sh);
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * k + j0 + c] = r;
     }
 }
 
@@ -215,7 +225,8 @@ void dev_dot(const Plan& P, const double* a, const double* b, int64_t len, doubl
 
 void dev_multidot(const Plan& P, const double* V, int64_t ld, int k, const double* w, int64_t len,
                   double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_multidot_partial, dim3(kRedBlocks), dim3(256), 0, s, V, ld, k, w, len, P.red);
+    hipLaunchKernelGGL(k_multidot_partial, dim3(kRedBlocks, (unsigned)((k + kDotCols - 1) / kDotCols)), dim3(256), 0,
+                       s, V, ld, k, w, len, P.red);
     SDBIE_LAUNCHED();
     hipLaunchKernelGGL(k_reduce_cols, dim3(k), dim3(256), 0, s, (const double*)P.red, kRedBlocks, k, out);
     SDBIE_LAUNCHED();

@@ -180,7 +180,7 @@ void sdbie_default_opts(sdbie_opts* o) {
 }
 
 size_t sdbie_workspace_bytes(int64_t n, int max_restart) {
-    if (n < 1 || n > kMaxNodes || max_restart < 1 || max_restart > 200) return 0;
+    if (n < 1 || n > kMaxNodes || max_restart < 1 || max_restart > kMaxRestart) return 0;
     return workspace_bytes(n, max_restart);
 }
 
@@ -197,7 +197,7 @@ int sdbie_plan_create(sdbie_plan* out, const sdbie_surface* s, int max_restart, 
         if (s->n < 1 || s->n > kMaxNodes) fail(SDBIE_ERR_ARG, "n must lie in [1, 2^23]");
         check_finite_pos(s->delta, "delta");
         if (s->delta < kMinDelta || s->delta > kMaxCoord) fail(SDBIE_ERR_ARG, "delta must lie in [1e-15, 1e15]");
-        if (max_restart < 1 || max_restart > 200) fail(SDBIE_ERR_ARG, "max_restart must lie in [1, 200]");
+        if (max_restart < 1 || max_restart > kMaxRestart) fail(SDBIE_ERR_ARG, "max_restart must lie in [1, 1000]");
         if (!ws) fail(SDBIE_ERR_WORKSPACE, "null workspace");
         if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) fail(SDBIE_ERR_WORKSPACE, "workspace not 256-byte aligned");
         const size_t need = workspace_bytes(s->n, max_restart);

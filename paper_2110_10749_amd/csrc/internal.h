@@ -33,6 +33,7 @@ constexpr int kMaxSplit = 64;    // source splits of one pair pass
 constexpr int64_t kMaxNodes = (int64_t)1 << 23;  // the tile-pair masks grow as (n/256)^2 bytes
 constexpr int kNearUnit = 64;    // sources per work unit of the near-field kernel
 constexpr int kRecBytes = 128;   // largest per-source record of a pair pass
+constexpr int kMaxRestart = 1000; // largest GMRES restart length of a plan
 // accepted input range: |coordinates| <= kMaxCoord, delta in [kMinDelta, kMaxCoord],
 // so every pair distance squared is a normal number in float and double
 constexpr double kMaxCoord = 1e15;

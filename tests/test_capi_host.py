@@ -51,7 +51,7 @@ def test_workspace_bytes(L):
     assert binding.workspace_bytes(68166, 10) < b
     assert binding.workspace_bytes(0, 50) == 0
     assert binding.workspace_bytes(100, 0) == 0
-    assert binding.workspace_bytes(100, 1000) == 0
+    assert binding.workspace_bytes(100, 1000) > 0 and binding.workspace_bytes(100, 1001) == 0
 
 
 def test_invalid_arguments_are_rejected_on_the_host(L):

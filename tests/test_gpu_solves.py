@@ -197,6 +197,24 @@ def test_mixed_matches_fp64_at_solver_tolerances(sd, inv_h, K, alpha, mode):
     assert abs(D64[2] - De) / De < 2e-4
 
 
+def test_large_slip_with_long_restart(sd, s16):
+    # beta = alpha mu / sqrt(K) = 100: the implicit-slip Stokes operator is
+    # indefinite (the smoothed Stokeslet matrix has small negative eigenvalues,
+    # -0.022 at h = 1/8, which beta multiplies), so restarted GMRES(50) stalls;
+    # a long restart converges.  Both precisions against the oracle's dense
+    # direct solve of the coupled system (condition number ~1e3 here).
+    S, geo, ops, plan0 = s16
+    K, alpha = 1e-2, 10.0
+    pb, ub, Db = O.coupled_dense_solve(geo, O.Params(1.0, K, alpha), E)
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), geo.delta, max_restart=600)
+    for prec in ("fp64", "mixed"):
+        p, u, D, info = sd.ddm_solve(plan, 1.0, K, alpha, E, None,
+                                     opts=dict(prec=prec, restart=600, maxit_gmres=3000))
+        print(prec, info, rel(host(u), ub), rel(host(p), pb), rel(D, Db), flush=True)
+        assert info["converged"]
+        assert rel(host(u), ub) < 1e-6 and rel(host(p), pb) < 1e-6 and rel(D, Db) < 1e-7
+
+
 def test_mixed_benchmark_mode_with_forcing(sd, s16):
     S, geo, ops, plan = s16
     fx = exact.jt_viscous_traction(S.x, E, K=1e-2)
