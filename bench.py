@@ -19,7 +19,11 @@ durations recorded by the library around every pair-sum kernel during the timed
 region), and the CPU oracle's pair rate on a bounded sample of target rows of
 the same surface.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload sphere-h64|perturbed-h128]
+
+The second workload is the large surface (N = 351866); one solve takes minutes,
+so run it with --steps 1 --warmup 0 --no-fp64 (SDBIE_DEBUG=1 prints the
+interface steps as they complete).
 """
 from __future__ import annotations
 
@@ -112,7 +116,10 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--inv-h", type=int, default=64)
+    ap.add_argument("--workload", choices=["sphere-h64", "perturbed-h128"], default="sphere-h64",
+                    help="sphere-h64: the porous unit sphere at h=1/64 (N=68166), K=1e-2, U=e_z (closed-form "
+                         "drag); perturbed-h128: a sphere perturbed by degree<=8 harmonics (seeded, sigma 0.05) "
+                         "at h=1/128 (N=351866), K=1e-3, U seeded on the unit sphere")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -145,16 +152,26 @@ def main() -> int:
         return 1
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
-    h = 1.0 / args.inv_h
+    from workloads import fields
+    mu, alpha = 1.0, 1.0
+    if args.workload == "sphere-h64":
+        h, K = 1.0 / 64, 1e-2
+        E = [0.0, 0.0, 1.0]
+        S = surfaces.sphere(h)
+        D_exact = exact.bjs_drag(K=K, beta=alpha * mu / math.sqrt(K))
+        wl = (f"porous unit sphere, h=1/64 (N={S.N}), delta=3h, U=e_z, mu=1, K=1e-2, alpha=1")
+    else:
+        h, K = 1.0 / 128, 1e-3
+        E = [float(v) for v in fields.unit_vector(53)]
+        S = surfaces.perturbed_sphere(h, lmax=8, sigma=0.05, seed=0)
+        D_exact = None
+        wl = (f"sphere perturbed by degree<=8 real harmonics (N(0,0.05^2) coefficients, seed 0), h=1/128 "
+              f"(N={S.N}), delta=3h, U={np.round(E, 4).tolist()}, mu=1, K=1e-3, alpha=1")
     delta = 3 * h
-    mu, K, alpha = 1.0, 1e-2, 1.0
-    beta = alpha * mu / math.sqrt(K)
-    E = [0.0, 0.0, 1.0]
-    S = surfaces.sphere(h)
     plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), delta)
     opts_mixed = dict(prec="mixed", outer="gmres", tol_gmres=1e-10, tol_ddm=1e-8)
     opts_fp64 = dict(prec="fp64", outer="gmres", tol_gmres=1e-10, tol_ddm=1e-8)
-    D_exact = exact.bjs_drag(K=K, beta=beta)
+    flow = lambda D: float(np.dot(D, E))
 
     for _ in range(args.warmup):
         sd.ddm_solve(plan, mu, K, alpha, E, None, opts=opts_mixed)
@@ -169,13 +186,13 @@ def main() -> int:
         p, u, D, info = sd.ddm_solve(plan, mu, K, alpha, E, None, opts=opts_mixed)
         pairs += info["pairs"]
         infos.append(info)
-        log(f"step {k}: drag {D[2]:.12f} info {info}")
+        log(f"step {k}: drag {flow(D):.12f} info {info}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stats = sd.profile_read()
     sd.profile_enable(False)
     wall = t1 - t0
-    D_mixed = D[2]
+    D_mixed = flow(D)
 
     # dominant kernel over the timed region
     dom = max(stats, key=lambda s: s["ms"])
@@ -207,16 +224,15 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32-pairs+f64",
         "data": "synthetic",
-        "config": {"workload": f"porous unit sphere, h=1/{args.inv_h} (N={S.N}), delta=3h, U=e_z, mu=1, "
-                               f"K=1e-2, alpha=1; ddm_solve with interface GMRES (tol 1e-8, inexact products), "
-                               f"local GMRES tol 1e-10 (float pairs below residual 1e-4, double true residuals)",
+        "config": {"workload": wl + "; ddm_solve with interface GMRES (tol 1e-8, inexact products), local "
+                               "GMRES tol 1e-10 (float pairs below residual 1e-4, double true residuals)",
                    "N": S.N, "pairs_per_step": pairs / args.steps},
         "roofline": roofline,
         "kernels": stats,
         "kernel_time_frac": kernel_ms_total * 1e-3 / wall,
         "drag_mixed": D_mixed,
         "drag_exact": D_exact,
-        "drag_rel_err_mixed": abs(D_mixed - D_exact) / D_exact,
+        "drag_rel_err_mixed": None if D_exact is None else abs(D_mixed - D_exact) / D_exact,
         "mixed_info": infos[-1],
     }
 
@@ -234,16 +250,16 @@ def main() -> int:
         result.update({
             "fp64_strict_ms_per_solve": 1e3 * t64s,
             "speedup_mixed_vs_fp64_strict": t64s / (wall / args.steps),
-            "drag_fp64_strict": D64s[2],
+            "drag_fp64_strict": flow(D64s),
             "fp64_strict_info": info64s,
         })
         result.update({
             "fp64_ms_per_solve": 1e3 * t64,
             "fp64_pairs_per_s": info64["pairs"] / t64,
             "speedup_mixed_vs_fp64": t64 / (wall / args.steps),
-            "drag_fp64": D64[2],
-            "drag_rel_err_fp64": abs(D64[2] - D_exact) / D_exact,
-            "drag_rel_diff_mixed_vs_fp64": abs(D_mixed - D64[2]) / abs(D64[2]),
+            "drag_fp64": flow(D64),
+            "drag_rel_err_fp64": None if D_exact is None else abs(flow(D64) - D_exact) / D_exact,
+            "drag_rel_diff_mixed_vs_fp64": abs(D_mixed - flow(D64)) / abs(flow(D64)),
             "u_max_rel_diff_mixed_vs_fp64": float((u - u64).abs().max() / u64.abs().max()),
             "p_max_rel_diff_mixed_vs_fp64": float((p - p64).abs().max() / p64.abs().max()),
             "fp64_info": info64,

@@ -102,6 +102,40 @@ def cutoff(ks, eps):
     return 0.0
 
 
+def erfcx_fit(lo, hi, p, deg, ctype):
+    """Coefficients (low to high) of a polynomial g(t), t = 1/(1 + p rho), with
+    g ~ erfc(rho) exp(rho^2) on [lo, hi]: interpolation at the Chebyshev
+    points of the t interval in 60-digit arithmetic.  Returns (coefficients,
+    max relative error of Horner's rule in the target precision on a grid)."""
+    import numpy as np
+    with mp.workdps(60):
+        tlo, thi = 1 / (1 + p * mp.mpf(hi)), 1 / (1 + p * mp.mpf(lo))
+        tm, th = (tlo + thi) / 2, (thi - tlo) / 2
+        nodes = [tm + th * mp.cos(mp.pi * (k + mp.mpf(1) / 2) / (deg + 1)) for k in range(deg + 1)]
+        vals = [mp.erfc((1 / t - 1) / p) * mp.exp(((1 / t - 1) / p) ** 2) for t in nodes]
+        A = mp.matrix([[t ** j for j in range(deg + 1)] for t in nodes])
+        c = mp.lu_solve(A, mp.matrix(vals))
+        coef = [c[j] for j in range(deg + 1)]
+        dt = np.float64 if ctype == "double" else np.float32
+        cc = [dt(float(v)) for v in coef]
+        worst = 0.0
+        for r in np.linspace(lo, hi, 3001):
+            r = dt(r)
+            t = dt(1) / (dt(1) + dt(p) * r)
+            a = cc[-1]
+            for v in reversed(cc[:-1]):
+                a = a * t + v
+            ex = mp.erfc(mp.mpf(float(r))) * mp.exp(mp.mpf(float(r)) ** 2)
+            worst = max(worst, abs(float((mp.mpf(float(a)) - ex) / ex)))
+    return coef, worst
+
+
+def emit_plain(name, vals, ctype, suffix):
+    body = ",\n    ".join(mp.nstr(v, 25, min_fixed=-1, max_fixed=-1) + suffix for v in vals)
+    return f"static constexpr int {name}_N = {len(vals)};\n" \
+           f"__device__ static constexpr {ctype} {name}[{len(vals)}] = {{\n    {body}}};\n"
+
+
 def emit(name, coef, ctype, suffix):
     c = c_mp()
     vals = [mp.mpf(a.numerator) / a.denominator * c for a in coef]
@@ -111,7 +145,10 @@ def emit(name, coef, ctype, suffix):
 
 
 def main():
-    rho_s64, rho_s32 = 0.5, 0.5
+    # series below rho_s; above it erf = 1 - exp(-rho^2) g(1/(1 + p rho)).
+    # Float starts the fit at rho = 1, where every s_k >= 0.3, so the rounding
+    # of t (amplified by 1/(1 - t) in g) stays near one ulp of s_k.
+    rho_s64, rho_s32 = 0.5, 1.0
     eps64, eps32 = 2.0**-54, 2.0**-25
     out = ["// Generated by gen_smoothing.py; do not edit.",
            "// Taylor coefficients (in x = rho^2) of F1..F4 = s_k/rho^p and of",
@@ -123,6 +160,10 @@ def main():
     sto = cutoff([1, 3, 4], 2.0**-53)
     lap32 = cutoff([1, 2], 2.0**-24)
     sto32 = cutoff([1, 3, 4], 2.0**-24)
+    p_fit = 0.33
+    g64, e64 = erfcx_fit(rho_s64 - 0.01, sto + 0.1, p_fit, 16, "double")
+    g32, e32 = erfcx_fit(rho_s32 - 0.01, sto32 + 0.1, p_fit, 8, "float")
+    assert e64 < 1.5e-15 and e32 < 4e-7, (e64, e32)
     # the adjoint's derivative factors also need s2 and s4 -> 1
     out.append(f"#define SDBIE_RHO_CUT_LAPLACE_F64 {lap}")
     out.append(f"#define SDBIE_RHO_CUT_STOKES_F64 {sto}")
@@ -133,6 +174,12 @@ def main():
         a = F_series(k)
         out.append(emit(f"kF{k}_F64", truncate(a, rho_s64, eps64), "double", ""))
         out.append(emit(f"kF{k}_F32", truncate(a, rho_s32, eps32), "float", "f"))
+    out.append(f"// erfc(rho) exp(rho^2) ~ sum_j kERFCX_*[j] t^j, t = 1/(1 + SDBIE_ERFCX_P rho), on")
+    out.append(f"// [{rho_s64 - 0.01}, {sto + 0.1}] (double, max rel. error {e64:.1e}) and "
+               f"[{rho_s32 - 0.01}, {sto32 + 0.1}] (float, {e32:.1e})")
+    out.append(f"#define SDBIE_ERFCX_P {p_fit}")
+    out.append(emit_plain("kERFCX_F64", g64, "double", ""))
+    out.append(emit_plain("kERFCX_F32", g32, "float", "f"))
     for k in (2, 4):
         g = G_series(k)
         out.append(emit(f"kG{k}_F64", truncate(g, rho_s64, eps64), "double", ""))

@@ -13,8 +13,8 @@
 // branch is taken by few waves); the source range is cut into `nsplit` equal
 // chunks, one per block, with split = blockIdx.x % nsplit so that the
 // round-robin dispatch over the 8 XCDs gives each XCD a fixed subset of the
-// source chunks (and its L2 only those sources).  Sources are staged through
-// LDS in tiles of 256 (every lane then reads the same LDS word: a broadcast).
+// source chunks (and its L2 only those sources).  Source records are read at
+// wave-uniform addresses, through the scalar cache into SGPRs.
 // Partial sums per split go to a scratch array and an epilogue kernel adds
 // them in a fixed order (no atomics: results are bitwise reproducible).
 //
@@ -24,8 +24,10 @@
 //
 // Smoothing: for rho = r/delta below SDBIE_RHO_SERIES_* the factors are Taylor
 // series in rho^2 (the closed forms cancel there); between that and the far
-// cutoff they are the paper's erf/exp formulas; beyond the cutoff every s_k
-// equals 1 to within half an ulp of T and the plain 1/r^p kernels are used.
+// cutoff they are the paper's erf/exp formulas, with erf = 1 - exp(-rho^2)
+// erfcx(rho) and erfcx from a fitted polynomial (no branches inside erf);
+// beyond the cutoff every s_k equals 1 to within half an ulp of T and the
+// plain 1/r^p kernels are used.
 #include "internal.h"
 #include "smoothing_coeffs.h"
 
@@ -49,10 +51,15 @@ __device__ __forceinline__ float rsq_pos(float v) { return __builtin_amdgcn_rsqf
 // far-field pairs never reach r = 0; near-field pairs do (the self pair)
 template <bool NEAR, typename T>
 __device__ __forceinline__ T rsq_pair(T v) { return NEAR ? rsq(v) : rsq_pos(v); }
-__device__ __forceinline__ double erf_t(double v) { return erf(v); }
-__device__ __forceinline__ float erf_t(float v) { return erff(v); }
 __device__ __forceinline__ double exp_t(double v) { return exp(v); }
 __device__ __forceinline__ float exp_t(float v) { return __expf(v); }
+// 1/v for v in [1, 4] (no special cases): hardware estimate, two Newton steps in double
+__device__ __forceinline__ double rcp_t(double v) {
+    double y = __builtin_amdgcn_rcp(v);
+    y = fma(fma(-v, y, 1.0), y, y);
+    return fma(fma(-v, y, 1.0), y, y);
+}
+__device__ __forceinline__ float rcp_t(float v) { return __builtin_amdgcn_rcpf(v); }
 
 template <typename T, int N>
 __device__ __forceinline__ T horner(const T (&c)[N], T x) {
@@ -62,6 +69,16 @@ __device__ __forceinline__ T horner(const T (&c)[N], T x) {
     return a;
 }
 
+__device__ __forceinline__ double erfcx_fit(double t) { return horner(kERFCX_F64, t); }
+__device__ __forceinline__ float erfcx_fit(float t) { return horner(kERFCX_F32, t); }
+// erf(rho) for rho between the series branch point and the far cutoff, given
+// E = exp(-rho^2): erf = 1 - E erfcx(rho), with erfcx from its fitted
+// polynomial in t = 1/(1 + p rho) (branch-free; smoothing_coeffs.h)
+template <typename T>
+__device__ __forceinline__ T erf_near(T rho, T E) {
+    const T t = rcp_t(fma(T(SDBIE_ERFCX_P), rho, T(1)));
+    return fma(-E, erfcx_fit(t), T(1));
+}
 __device__ __forceinline__ double ser_F1(double x) { return horner(kF1_F64, x); }
 __device__ __forceinline__ double ser_F2(double x) { return horner(kF2_F64, x); }
 __device__ __forceinline__ double ser_F3(double x) { return horner(kF3_F64, x); }
@@ -97,8 +114,9 @@ __device__ __forceinline__ void near_factors(T r2, T inv_r, T id, T id2, T& k1, 
         if (K4) k4 = ser_F4(x) * id3 * id2;
     } else {
         const T rho = r2 * inv_r * id;
-        const T ef = erf_t(rho);
-        const T cE = T(kTwoOverSqrtPi) * rho * exp_t(-x);
+        const T E = exp_t(-x);
+        const T ef = erf_near(rho, E);
+        const T cE = T(kTwoOverSqrtPi) * rho * E;
         const T ir2 = inv_r * inv_r;
         const T third = T(1.0 / 3.0);
         if (K1) k1 = (ef - cE * third * (T(2) * x - T(5))) * inv_r;
@@ -448,8 +466,8 @@ __device__ __forceinline__ void near_G(double r2, double inv_r, double id, doubl
         g4 = horner(kG4_F64, x) * id5 * id2;
     } else {
         const double rho = r2 * inv_r * id;
-        const double ef = erf(rho);
         const double E = exp(-x);
+        const double ef = erf_near(rho, E);
         const double cE = kTwoOverSqrtPi * rho * E;
         const double ir2 = inv_r * inv_r;
         const double s2 = ef + cE * (1.0 / 3.0) * (2.0 * x - 3.0);

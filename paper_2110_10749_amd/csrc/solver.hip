@@ -409,6 +409,7 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
     dev_normal_component(P, ul, t0, s);
     const double t0n = relax ? norm(t0, n) : 0.0;
     double tol_cyc = tol;  // relative tolerance of the current cycle
+    int outer_steps = 0;
     auto op = [&](const double* y, double* out, bool, double rr) {
         const double tl_save = tol_local;
         const bool l_save = loose32;
@@ -417,6 +418,10 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
             tol_local = tl;
             loose32 = o.prec == SDBIE_MIXED && tl >= kLooseFloat;
         }
+        if (debug_level() >= 1)
+            std::fprintf(stderr, "[sdbie] interface step %d: residual %.3e, local tolerance %.1e%s\n",
+                         ++outer_steps, rr, tol_local > 0.0 ? tol_local : o.tol_gmres,
+                         loose32 ? " (float pairs)" : "");
         darcy(prm, y, pl, false, nullptr, remove_mean);
         const double* ps = pl;
         if (!remove_mean) {
@@ -449,6 +454,7 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
         dev_axpby(1.0, pl, -1.0, v, pl, n, s);
         const double rt = norm(pl, n) / t0n;
         info.ddm_res = rt;
+        if (debug_level() >= 1) std::fprintf(stderr, "[sdbie] true interface residual %.3e\n", rt);
         conv = rt <= tol;
         if (conv || cyc >= kOuterCycles || info.ddm_iters >= o.maxit_ddm) break;
         // correction cycle: (I - T_lin) d = u.n - v, relative tolerance tol / rt

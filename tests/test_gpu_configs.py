@@ -1,0 +1,180 @@
+"""The benchmark configurations beyond the unit sphere, on the GPU.
+
+* Ellipsoid x^2 + y^2/0.64 + z^2/0.36 = 1 and a sphere radially perturbed by
+  real harmonics of degree <= 4 (seeded N(0, 0.05^2) coefficients), h = 1/64,
+  delta = 3h: every layer kind in both precisions against the oracle on
+  sampled target rows; the mixed ddm_solve (U uniform on the unit sphere,
+  seeded; K = 1e-2, alpha = 1) against the FP64 GPU path; self-convergence of
+  the mixed solve over h = 1/16, 1/32, 1/64 on the nested node sets (the nodes
+  at h are the nodes at h/2 on every second grid line).
+* The gradient of drag on the perturbed sphere with respect to log K, alpha
+  and 20 seeded node-coordinate directions against central differences of the
+  FP64 forward solve (step 1e-6, tight tolerances): at h = 1/32 always, at
+  h = 1/64 (the configuration's size, ~8 minutes) with SDBIE_LONG_TESTS=1.
+* The large perturbed sphere (degree <= 8, h = 1/128, N = 351866), K = 1e-3,
+  alpha = 1: sampled rows, and local Darcy and Stokes solves in both
+  precisions.
+"""
+import math
+import os
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_check import check_all_layers, dev
+from oracle import oracle as O
+from workloads import fields, surfaces
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = dict(prec="fp64", tol_gmres=1e-13, tol_ddm=1e-12)
+
+
+@pytest.fixture(scope="module")
+def sd():
+    import paper_2110_10749_amd as sd
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return sd
+
+
+def make_surface(kind, h):
+    if kind == "ellipsoid":
+        return surfaces.ellipsoid(h, 1.0, 0.8, 0.6)
+    return surfaces.perturbed_sphere(h, lmax=4, sigma=0.05, seed=0)
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b))) / max(np.max(np.abs(b)), 1e-300))
+
+
+def common_nodes(xa, xb):
+    """Indices (ia, ib) of the nodes of xa that are also nodes of xb."""
+    key = lambda x: [tuple(v) for v in np.round(x.T, 11)]
+    pos = {k: j for j, k in enumerate(key(xb))}
+    ia, ib = [], []
+    for i, k in enumerate(key(xa)):
+        j = pos.get(k)
+        if j is not None:
+            ia.append(i)
+            ib.append(j)
+    return np.array(ia), np.array(ib)
+
+
+@pytest.mark.parametrize("kind", ["ellipsoid", "perturbed"])
+def test_layers_sampled_rows(sd, kind):
+    S = make_surface(kind, 1.0 / 64)
+    rng = np.random.default_rng(21)
+    t = np.sort(rng.choice(S.N, size=192, replace=False))
+    check_all_layers(sd, S.x, S.n, S.w, 3.0 / 64, seed=22, targets=t)
+
+
+@pytest.mark.parametrize("kind", ["ellipsoid", "perturbed"])
+def test_mixed_solve_and_self_convergence(sd, kind):
+    U = fields.unit_vector(31)
+    K, alpha = 1e-2, 1.0
+    sols = {}
+    for inv_h in (16, 32, 64):
+        S = make_surface(kind, 1.0 / inv_h)
+        plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / inv_h)
+        t0 = time.perf_counter()
+        p, u, D, info = sd.ddm_solve(plan, 1.0, K, alpha, U, None, opts=dict(prec="mixed"))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(kind, inv_h, S.N, "mixed", D, info, f"{dt:.2f} s", flush=True)
+        assert info["converged"]
+        if inv_h == 64:
+            p64, u64, D64, i64 = sd.ddm_solve(plan, 1.0, K, alpha, U, None, opts=dict(prec="fp64"))
+            print(kind, "fp64", D64, i64, flush=True)
+            assert i64["converged"]
+            assert rel(D, D64) < 1e-8
+            assert rel(host(u), host(u64)) < 1e-7 and rel(host(p), host(p64)) < 1e-7
+        sols[inv_h] = (S.x, host(p), host(u), np.asarray(D))
+        plan.close()
+    # self-convergence on the nested node sets (unweighted RMS differences)
+    diffs = []
+    for a, b in ((16, 32), (32, 64)):
+        ia, ib = common_nodes(sols[a][0], sols[b][0])
+        assert len(ia) == sols[a][0].shape[1]  # every coarse node is a fine node
+        dp = np.sqrt(np.mean((sols[a][1][ia] - sols[b][1][ib]) ** 2))
+        du = np.sqrt(np.mean((sols[a][2][:, ia] - sols[b][2][:, ib]) ** 2))
+        dD = abs(np.dot(sols[a][3] - sols[b][3], U)) / abs(np.dot(sols[b][3], U))
+        diffs.append((dp, du, dD))
+        print(kind, f"h=1/{a} vs 1/{b}: p {dp:.3e} u {du:.3e} drag {dD:.3e}", flush=True)
+    (dp1, du1, _), (dp2, du2, dD2) = diffs
+    assert dp2 < dp1 / 4 and du2 < du1 / 4  # at least second order between the two halvings
+    assert dp2 < 1e-3 and du2 < 1e-3 and dD2 < 1e-3
+
+
+LONG = os.environ.get("SDBIE_LONG_TESTS") == "1"
+
+
+@pytest.mark.parametrize("inv_h", [32, pytest.param(64, marks=pytest.mark.skipif(
+    not LONG, reason="42 tight FP64 solves at N = 71002 take ~8 minutes; set SDBIE_LONG_TESTS=1"))])
+def test_adjoint_perturbed_central_differences(sd, inv_h):
+    S = make_surface("perturbed", 1.0 / inv_h)
+    delta = 3.0 / inv_h
+    K, alpha = 1e-2, 1.0
+    U = fields.unit_vector(41)
+    e = fields.unit_vector(42)
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), delta)
+
+    def J(x=None, K=K, alpha=alpha):
+        pl = plan if x is None else sd.Plan(dev(x), dev(S.n), dev(S.w), delta)
+        _, _, D, info = sd.ddm_solve(pl, 1.0, K, alpha, U, None, opts=TIGHT)
+        assert info["converged"]
+        if x is not None:
+            pl.close()
+        return float(np.dot(e, D))
+
+    p, u, D, info = sd.ddm_solve(plan, 1.0, K, alpha, U, None, opts=TIGHT)
+    gx, gK, ga, ainfo = sd.ddm_adjoint(plan, 1.0, K, alpha, U, p, u, e, None, opts=TIGHT)
+    assert ainfo["converged"]
+    gx = host(gx)
+    hs = 1e-6
+    fdK = (J(K=K * math.exp(hs)) - J(K=K * math.exp(-hs))) / (2 * hs)
+    fda = (J(alpha=alpha + hs) - J(alpha=alpha - hs)) / (2 * hs)
+    print("logK", gK, fdK, "alpha", ga, fda, flush=True)
+    assert abs(gK - fdK) < 1e-5 * abs(fdK)
+    assert abs(ga - fda) < 1e-5 * abs(fda)
+    worst = 0.0
+    for k in range(20):
+        V = fields.random_vector(S.N, 300 + k)
+        fd = (J(S.x + hs * V) - J(S.x - hs * V)) / (2 * hs)
+        ad = float((gx * V).sum())
+        err = abs(ad - fd) / max(abs(fd), 1e-3)
+        worst = max(worst, err)
+        print("direction", k, ad, fd, f"{err:.1e}", flush=True)
+    assert worst < 1e-4
+
+
+def test_large_perturbed_sphere_h128(sd):
+    t0 = time.perf_counter()
+    S = surfaces.perturbed_sphere(1.0 / 128, lmax=8, sigma=0.05, seed=0)
+    print("N", S.N, f"generated in {time.perf_counter() - t0:.1f} s", flush=True)
+    delta = 3.0 / 128
+    rng = np.random.default_rng(51)
+    t = np.sort(rng.choice(S.N, size=48, replace=False))
+    check_all_layers(sd, S.x, S.n, S.w, delta, seed=52, targets=t)
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), delta)
+    U = fields.unit_vector(53)
+    K, alpha = 1e-3, 1.0
+    # one local Darcy and one local Stokes solve (the full interface solve at
+    # this size is a benchmark workload: bench.py --workload perturbed-h128)
+    v = dev(fields.smooth_scalar(S.x, 54))
+    res = {}
+    for prec in ("mixed", "fp64"):
+        t0 = time.perf_counter()
+        p, ip = sd.darcy_solve(plan, 1.0, K, alpha, v, opts=dict(prec=prec))
+        u, iu = sd.stokes_solve(plan, 1.0, K, alpha, U, p, opts=dict(prec=prec))
+        torch.cuda.synchronize()
+        print(prec, ip, iu, f"{time.perf_counter() - t0:.2f} s", flush=True)
+        assert ip["converged"] and iu["converged"]
+        res[prec] = (host(p), host(u))
+    assert rel(res["mixed"][0], res["fp64"][0]) < 1e-8
+    assert rel(res["mixed"][1], res["fp64"][1]) < 1e-8

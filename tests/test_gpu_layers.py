@@ -17,16 +17,11 @@ import numpy as np
 import pytest
 import torch
 
+from gpu_check import TOL32, check_all_layers, dev, make_plan, relerr
 from oracle import oracle as O
 from workloads import fields, surfaces
 
 pytestmark = pytest.mark.gpu
-
-TOL64 = 1e-12
-TOL32 = 3e-6
-EPS32 = 2.0**-24
-
-LAYERS = [("sl", O.LSL, O.SSL), ("dl_raw", O.LDL, O.SDL), ("dl_sub", O.LDLS, O.SDLS)]
 
 
 @pytest.fixture(scope="module")
@@ -34,45 +29,6 @@ def sd():
     import paper_2110_10749_amd as sd
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     return sd
-
-
-def dev(a):
-    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
-
-
-def relerr(got, ref):
-    return float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300))
-
-
-def make_plan(sd, x, n, w, delta):
-    return sd.Plan(dev(x), dev(n), dev(w), delta)
-
-
-def check_all_layers(sd, x, n, w, delta, seed, mu=1.3, targets=None, precs=("fp64", "mixed")):
-    N = w.shape[0]
-    geo = O.Geometry(x, n, w, delta)
-    plan = make_plan(sd, x, n, w, delta)
-    q = fields.random_scalar(N, seed)
-    u = fields.random_vector(N, seed + 1)
-    out = {}
-    for name, lk, sk in LAYERS:
-        ref_l = O.laplace_apply(geo, lk, q, targets)
-        ref_s = O.stokes_apply(geo, mu, sk, u, targets)
-        for prec in precs:
-            gl = sd.laplace_layer_apply(plan, name, dev(q), prec=prec).cpu().numpy()
-            gs = sd.stokes_layer_apply(plan, mu, name, dev(u), prec=prec).cpu().numpy()
-            if targets is not None:
-                gl, gs = gl[targets], gs[:, targets]
-            el, es = relerr(gl, ref_l), relerr(gs, ref_s)
-            tol = TOL64 if prec == "fp64" else TOL32
-            if prec == "mixed" and name == "dl_raw":
-                tol = max(TOL32, 4 * EPS32 * np.max(np.abs(x)) / delta**2)
-            print(f"N={N} {name:7s} {prec:5s} laplace {el:.2e} stokes {es:.2e}", flush=True)
-            assert el < tol, (name, prec, "laplace", el)
-            assert es < tol, (name, prec, "stokes", es)
-            out[(name, prec)] = (el, es)
-    plan.close()
-    return out
 
 
 def test_sphere_h16(sd):

@@ -111,24 +111,66 @@ def _line_coords(i: int, a: np.ndarray, b: np.ndarray, t: np.ndarray) -> np.ndar
     return x
 
 
-def _bracket_roots(phi, i, a, b, t_lo, t_hi, dt, grad_phi=None, bisect=80):
+def _sample_sign_changes(phi, i, a, b, t_lo, t_hi, nsamp, lip):
+    """Brackets (line, sample index, t_k, t_k+1, phi(t_k)) of every sign change
+    of phi between consecutive samples t_k = t_lo + k (t_hi - t_lo)/(nsamp - 1).
+
+    With lip (a bound on |d phi/dt| along the lines) each line is walked over
+    the same samples, skipping ahead from t_k by floor(|phi(t_k)| / (lip dt))
+    samples: phi has no zero within |phi(t_k)| / lip of t_k, so every skipped
+    sample has the sign of phi(t_k) and the brackets are those of evaluating
+    every sample.
+    """
+    s = np.linspace(0.0, 1.0, nsamp)
+    span = t_hi - t_lo
+    if lip is None:
+        T = t_lo[:, None] + span[:, None] * s[None, :]
+        F = phi(_line_coords(i, np.broadcast_to(a[:, None], T.shape), np.broadcast_to(b[:, None], T.shape), T))
+        li, si = np.nonzero(np.signbit(F[:, :-1]) != np.signbit(F[:, 1:]))
+        return li, si, T[li, si], T[li, si + 1], F[li, si]
+    nl = span.shape[0]
+    step_len = span / (nsamp - 1)
+    k = np.zeros(nl, dtype=np.int64)
+    kp = np.full(nl, -2, dtype=np.int64)
+    tp = np.zeros(nl)
+    fp = np.zeros(nl)
+    act = np.arange(nl)
+    out = []
+    while act.size:
+        kk = k[act]
+        t = t_lo[act] + span[act] * s[kk]
+        f = phi(_line_coords(i, a[act], b[act], t))
+        hit = (kp[act] == kk - 1) & (np.signbit(f) != np.signbit(fp[act]))
+        if hit.any():
+            h_ = act[hit]
+            out.append((h_, kk[hit] - 1, tp[h_], t[hit], fp[h_]))
+        kp[act], tp[act], fp[act] = kk, t, f
+        adv = np.maximum(1, np.floor(np.abs(f) / (lip * step_len[act]))).astype(np.int64)
+        k[act] = kk + adv
+        act = act[k[act] <= nsamp - 1]
+    if not out:
+        e = np.zeros(0)
+        return np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.int64), e, e, e
+    li = np.concatenate([o[0] for o in out])
+    si = np.concatenate([o[1] for o in out])
+    lo = np.concatenate([o[2] for o in out])
+    hi = np.concatenate([o[3] for o in out])
+    fl = np.concatenate([o[4] for o in out])
+    order = np.lexsort((si, li))
+    return li[order], si[order], lo[order], hi[order], fl[order]
+
+
+def _bracket_roots(phi, i, a, b, t_lo, t_hi, dt, grad_phi=None, bisect=80, lip=None):
     """All sign changes of phi along lines (a_k, b_k, t), t in [t_lo_k, t_hi_k].
 
-    Sampled with step dt, then refined by bisection and, when the gradient
-    is given, by safeguarded Newton steps along the line to full precision.
+    Sampled with step dt (see _sample_sign_changes for the use of lip), then
+    refined by bisection and, when the gradient is given, by safeguarded
+    Newton steps along the line to full precision.
     Returns (line index, t) of every root found.
     """
     nsamp = int(np.max(np.ceil((t_hi - t_lo) / dt))) + 1
-    s = np.linspace(0.0, 1.0, nsamp)
-    T = t_lo[:, None] + (t_hi - t_lo)[:, None] * s[None, :]
-    A = np.broadcast_to(a[:, None], T.shape)
-    B = np.broadcast_to(b[:, None], T.shape)
-    F = phi(_line_coords(i, A, B, T))
-    sign_change = np.signbit(F[:, :-1]) != np.signbit(F[:, 1:])
-    li, si = np.nonzero(sign_change)
-    lo = T[li, si].copy()
-    hi = T[li, si + 1].copy()
-    flo = F[li, si].copy()
+    li, si, lo, hi, flo = _sample_sign_changes(phi, i, a, b, t_lo, t_hi, nsamp, lip)
+    lo, hi, flo = lo.copy(), hi.copy(), flo.copy()
     aa, bb = a[li], b[li]
     nb = bisect if grad_phi is None else 14
     for _ in range(nb):
@@ -150,7 +192,7 @@ def _bracket_roots(phi, i, a, b, t_lo, t_hi, dt, grad_phi=None, bisect=80):
     return li, t
 
 
-def _implicit_surface(phi, grad_phi, h, extent, shell=None, dt_factor=0.5):
+def _implicit_surface(phi, grad_phi, h, extent, shell=None, dt_factor=0.5, lip=None):
     """Node families R_1..R_3 of the level set phi = 0 (phi > 0 outside).
 
     `extent` bounds the body in every coordinate.  `shell = (rmin, rmax)`
@@ -177,7 +219,7 @@ def _implicit_surface(phi, grad_phi, h, extent, shell=None, dt_factor=0.5):
             for sgn in (-1.0, 1.0):
                 lo = np.where(sgn < 0, -tmax, tmin)
                 hi = np.where(sgn < 0, -tmin, tmax)
-                li, t = _bracket_roots(phi, i, a, b, lo, hi, h * dt_factor, grad_phi)
+                li, t = _bracket_roots(phi, i, a, b, lo, hi, h * dt_factor, grad_phi, lip=lip)
                 lis.append(li)
                 ts.append(t)
             li, t = np.concatenate(lis), np.concatenate(ts)
@@ -274,8 +316,9 @@ def _sh_collect(terms, coef):
     return out
 
 
-def _sh_eval(folded, u):
-    """r(u) = 1 + sum c_lm Y_lm(u) and its gradient w.r.t. u (u: (3, ...))."""
+def _sh_eval(folded, u, with_grad=True):
+    """r(u) = 1 + sum c_lm Y_lm(u) and its gradient w.r.t. u (u: (3, ...);
+    the gradient is None when with_grad is false)."""
     ux, uy, uz = u
     wz = ux + 1j * uy
     lmax = max(abs(m) for m in folded)
@@ -283,21 +326,23 @@ def _sh_eval(folded, u):
     for _ in range(lmax):
         powers.append(powers[-1] * wz)
     val = np.ones(ux.shape)
-    grad = np.zeros((3,) + ux.shape)
+    grad = np.zeros((3,) + ux.shape) if with_grad else None
     for m, (q0, q1) in folded.items():
         am = abs(m)
         p0 = np.polynomial.polynomial.polyval(uz, q0)
-        p1 = np.polynomial.polynomial.polyval(uz, q1)
         zm = powers[am]
-        zm1 = am * powers[am - 1] if am > 0 else np.zeros_like(wz)
-        if m >= 0:
-            ang, dang_x, dang_y = zm.real, zm1.real, -zm1.imag
-        else:
-            ang, dang_x, dang_y = zm.imag, zm1.imag, zm1.real
+        ang = zm.real if m >= 0 else zm.imag
         val = val + p0 * ang
-        grad[0] += p0 * dang_x
-        grad[1] += p0 * dang_y
-        grad[2] += p1 * ang
+        if with_grad:
+            p1 = np.polynomial.polynomial.polyval(uz, q1)
+            zm1 = am * powers[am - 1] if am > 0 else np.zeros_like(wz)
+            if m >= 0:
+                dang_x, dang_y = zm1.real, -zm1.imag
+            else:
+                dang_x, dang_y = zm1.imag, zm1.real
+            grad[0] += p0 * dang_x
+            grad[1] += p0 * dang_y
+            grad[2] += p1 * ang
     return val, grad
 
 
@@ -317,16 +362,27 @@ def perturbed_sphere(h: float, lmax: int = 4, sigma: float = 0.05, seed: int = 0
     ph = np.linspace(0.0, 2 * math.pi, 361)
     TH, PH = np.meshgrid(th, ph, indexing="ij")
     U = np.stack([np.sin(TH) * np.cos(PH), np.sin(TH) * np.sin(PH), np.cos(TH)])
-    rv, _ = _sh_eval(folded, U)
+    rv, gv = _sh_eval(folded, U)
     spread = float(rv.max() - rv.min())
     rmin = max(float(rv.min()) - 0.1 * spread - 0.02, 0.05)
     rmax = float(rv.max()) + 0.1 * spread + 0.02
     if rmin < 0.2:
         raise ValueError("perturbation too large for a star-shaped surface")
+    # |grad phi| <= 1 + |tangential grad_u r| / |x|: a slope bound along the
+    # grid lines; the tangential gradient of r is sampled on a 0.25-degree
+    # grid (its own variation between samples is far below the 25% margin)
+    th2 = np.linspace(0.0, math.pi, 721)
+    ph2 = np.linspace(0.0, 2 * math.pi, 1441)
+    TH2, PH2 = np.meshgrid(th2, ph2, indexing="ij")
+    U2 = np.stack([np.sin(TH2) * np.cos(PH2), np.sin(TH2) * np.sin(PH2), np.cos(TH2)])
+    _, gv2 = _sh_eval(folded, U2)
+    gt = gv2 - U2 * (U2 * gv2).sum(axis=0, keepdims=True)
+    lip = 1.0 + 1.25 * float(np.sqrt((gt * gt).sum(axis=0)).max()) / rmin
+
 
     def phi(x):
         rr = np.sqrt((x * x).sum(axis=0))
-        val, _ = _sh_eval(folded, x / rr)
+        val, _ = _sh_eval(folded, x / rr, with_grad=False)
         return rr - val
 
     def grad_phi(x):
@@ -337,7 +393,7 @@ def perturbed_sphere(h: float, lmax: int = 4, sigma: float = 0.05, seed: int = 0
         proj = gu - u * (u * gu).sum(axis=0, keepdims=True)
         return u - proj / rr
 
-    P, Nn = _implicit_surface(phi, grad_phi, h, rmax, shell=(rmin, rmax), dt_factor=1.0)
+    P, Nn = _implicit_surface(phi, grad_phi, h, rmax, shell=(rmin, rmax), dt_factor=1.0, lip=lip)
     x, n, w = _assemble(P, Nn, h)
     return Surface(x, n, w, h, name=f"perturbed_sphere(l<={lmax},sigma={sigma},seed={seed})",
                    meta={"lmax": lmax, "sigma": sigma, "seed": seed, "coef": coef.tolist()})
