@@ -134,7 +134,7 @@ void sdbie_default_opts(sdbie_opts* o);
 
 /* Bytes of device workspace a plan for n nodes (1 <= n <= 2^23) and GMRES
  * restart length up to max_restart (1..1000) needs (0 if the arguments are
- * invalid).  Roughly 8 (30 + 3 max_restart) n + 128 n bytes plus (n/256)^2 * 2. */
+ * invalid).  Roughly (64 max_restart + 1400) n bytes plus (n/256)^2 * 2. */
 size_t sdbie_workspace_bytes(int64_t n, int max_restart);
 
 /* Stage a surface: spatial (Morton) ordering, double and float copies of the

@@ -24,7 +24,7 @@ int64_t next_pow2(int64_t n) {
 
 struct Layout {
     size_t x, nrm, w, wn, px, pn, pw, px32, boxes, uboxes, mask64, mask32, perm, keys, partial, rec, red, scal, vecs,
-        basis_in, basis_out, total;
+        basis_in, basis_out, image_out, total;
 };
 
 Layout layout(int64_t n, int m) {
@@ -58,6 +58,7 @@ Layout layout(int64_t n, int m) {
     L.vecs = take((size_t)kNumVec * 3 * n * d);
     L.basis_in = take((size_t)(m + 1) * 3 * n * d);
     L.basis_out = take((size_t)(m + 1) * n * d);
+    L.image_out = take((size_t)(m + 1) * 4 * n * d);
     L.total = off;
     return L;
 }
@@ -154,6 +155,7 @@ void carve_workspace(Plan& P, void* ws) {
     P.vecs = reinterpret_cast<double*>(b + L.vecs);
     P.basis_in = reinterpret_cast<double*>(b + L.basis_in);
     P.basis_out = reinterpret_cast<double*>(b + L.basis_out);
+    P.image_out = reinterpret_cast<double*>(b + L.image_out);
 }
 
 }  // namespace sdbie

@@ -34,6 +34,9 @@ constexpr int64_t kMaxNodes = (int64_t)1 << 23;  // the tile-pair masks grow as 
 constexpr int kNearUnit = 64;    // sources per work unit of the near-field kernel
 constexpr int kRecBytes = 128;   // largest per-source record of a pair pass
 constexpr int kMaxRestart = 1000; // largest GMRES restart length of a plan
+#ifndef SDBIE_SPLIT_TARGET
+#define SDBIE_SPLIT_TARGET 8192      // pair-kernel grids aim for at least this many blocks (fills the 8 waves per SIMD about 4 times at the benchmark size)
+#endif
 // accepted input range: |coordinates| <= kMaxCoord, delta in [kMinDelta, kMaxCoord],
 // so every pair distance squared is a normal number in float and double
 constexpr double kMaxCoord = 1e15;
@@ -114,6 +117,7 @@ struct Plan {
     double* vecs = nullptr;     // general work vectors, kNumVec x [3][n]
     double* basis_in = nullptr;   // inner GMRES basis [(max_restart+1)][3n]
     double* basis_out = nullptr;  // outer GMRES basis [(max_restart+1)][n]
+    double* image_out = nullptr;  // local solutions (p, u) of each outer basis vector [(max_restart+1)][4n]
     double* host_pinned = nullptr;  // not used (host buffers are plain)
     // (target, source) pairs of real nodes in the near tile pairs (double, float masks)
     double near_pairs64 = 0.0, near_pairs32 = 0.0;
@@ -123,7 +127,7 @@ struct Plan {
     double* vec(int k) const { return vecs + (size_t)k * 3 * n; }
 };
 
-constexpr int kNumVec = 28;
+constexpr int kNumVec = 30;
 
 size_t workspace_bytes(int64_t n, int max_restart);
 void carve_workspace(Plan& P, void* ws);

@@ -813,7 +813,7 @@ void launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int fami
 
 int choose_splits(int64_t n) {
     const int64_t tblocks = (n + kTPB - 1) / kTPB;
-    int64_t s = 8 * ((2048 + 8 * tblocks - 1) / (8 * tblocks));
+    int64_t s = 8 * ((SDBIE_SPLIT_TARGET + 8 * tblocks - 1) / (8 * tblocks));
     if (s > kMaxSplit) s = kMaxSplit;
     while (s > 1 && n / s < 64) s /= 2;
     return (int)(s < 1 ? 1 : s);

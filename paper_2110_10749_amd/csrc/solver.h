@@ -35,6 +35,8 @@ enum : int {
     kVecCoupledDP,    // mixed coupled refinement: pressure correction
     kVecCoupledDU,    // mixed coupled refinement: velocity correction
     kVecCoupledV,     // mixed coupled refinement: u.n / projected pressure
+    kVecImage,        // interface solve: (p, u) combined from the image basis (4n: two slots)
+    kVecImage2,
     kVecSpare,
 };
 static_assert(kVecSpare < kNumVec, "work-vector slots exceed the workspace");
@@ -56,6 +58,12 @@ struct GmresWS {
     double* w = nullptr;
     double* dcol = nullptr;
     double* dy = nullptr;
+    // optional image basis: the operator stores what it computed for basis
+    // vector k at W2 + k ld2 (Ctx::krylov_index tells it k), and every cycle
+    // adds W2 y to x2 with the same coefficients y as V y to x
+    double* W2 = nullptr;
+    int64_t ld2 = 0;
+    double* x2 = nullptr;
 };
 
 struct GmresOut {
@@ -80,6 +88,8 @@ struct Ctx {
     // loose32: every pass of the local solves (right-hand sides included) in float pairs
     double tol_local = 0.0;
     bool loose32 = false;
+    // index of the Krylov basis vector the operator is being applied to (-1: a residual)
+    int krylov_index = -1;
 
     Ctx(Plan& plan, hipStream_t st, const sdbie_opts& opts);
     void finish();

@@ -136,6 +136,7 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
     double* w = ws.w;
     const bool all32 = std::isinf(relax);
     if (x_nonzero) {
+        krylov_index = -1;
         op(x, r, all32, 0.0);
         dev_axpby(1.0, b, -1.0, r, r, L, s);
     } else {
@@ -144,6 +145,7 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
     }
     double beta = norm(r, L);
     res.relres = beta / bnorm;
+    const double rel0 = res.relres;
     const int m = restart;
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), e(m + 1), col(2 * (m + 1) + 1), y(m);
     auto Hat = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
@@ -158,7 +160,9 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
             double* vk = ws.V + (int64_t)k * L;
             const bool m32 = all32 || res.relres <= relax;
             cycle32 = cycle32 || m32;
+            krylov_index = k;
             op(vk, w, m32, res.relres);
+            krylov_index = -1;
             res.iters++;
             double* h1 = ws.dcol;
             double* h2 = ws.dcol + (k + 1);
@@ -200,9 +204,11 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
         }
         SDBIE_HIP(hipMemcpyAsync(ws.dy, y.data(), k_used * sizeof(double), hipMemcpyHostToDevice, s));
         dev_multi_axpy_add(ws.V, L, k_used, ws.dy, x, L, s);
+        if (ws.W2) dev_multi_axpy_add(ws.W2, ws.ld2, k_used, ws.dy, ws.x2, ws.ld2, s);
         const bool verify = cycle32 && !all32;
         if (!verify && (res.relres <= tol || res.iters >= maxit)) break;
         // restart from (or verify with) the true residual
+        krylov_index = -1;
         op(x, r, all32, 0.0);
         dev_axpby(1.0, b, -1.0, r, r, L, s);
         beta = norm(r, L);
@@ -212,8 +218,8 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
     res.conv = res.relres <= tol;
     SDBIE_HIP(hipStreamSynchronize(s));
     if (debug_level() > 1)
-        std::fprintf(stderr, "[sdbie] gmres L=%lld iters=%d relres=%.3e tol=%.1e\n", (long long)L, res.iters,
-                     res.relres, tol);
+        std::fprintf(stderr, "[sdbie] gmres L=%lld start %.1e iters=%d relres=%.3e tol=%.1e\n", (long long)L, rel0,
+                     res.iters, res.relres, tol);
     return res;
 }
 
@@ -393,6 +399,10 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
     double* pp = P.vec(kVecCoupledV);
     double* dv = P.vec(kVecVn);
     const bool relax = o.relax_outer != 0 && !corr;
+    // image basis: the local solutions of every interface product, combined
+    // with the GMRES coefficients into a warm start (p, u) for the final solves
+    const bool image = !corr;
+    double* img = P.vec(kVecImage);  // [p (n) | u (3n)]
     // t0 = T(0)
     if (r1) {
         dev_fill(0.0, v, n, s);
@@ -408,9 +418,17 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
     stokes(prm, U, pstk, fx, ul, false, r2);
     dev_normal_component(P, ul, t0, s);
     const double t0n = relax ? norm(t0, n) : 0.0;
+    if (image) {
+        copy(pl, img, n);  // p(0): zero without an extra Darcy right-hand side
+        copy(ul, img + n, 3 * n);
+        outer.W2 = P.image_out;
+        outer.ld2 = 4 * n;
+        outer.x2 = img;
+    }
     double tol_cyc = tol;  // relative tolerance of the current cycle
     int outer_steps = 0;
     auto op = [&](const double* y, double* out, bool, double rr) {
+        const int kslot = krylov_index;  // the local solves below run GMRES of their own
         const double tl_save = tol_local;
         const bool l_save = loose32;
         if (relax && rr > 0.0) {
@@ -423,25 +441,42 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
                          ++outer_steps, rr, tol_local > 0.0 ? tol_local : o.tol_gmres,
                          loose32 ? " (float pairs)" : "");
         darcy(prm, y, pl, false, nullptr, remove_mean);
+        double* slot = image && kslot >= 0 ? P.image_out + (int64_t)kslot * 4 * n : nullptr;
+        if (slot) {
+            // the Darcy solution before its weighted mean was removed: the
+            // solution of the completed equation, hence a warm start for it
+            copy(pl, slot, n);
+            dev_add_scaled_scalar(slot, P.scal + kScalMean, 1.0 / P.area, n, s);
+        }
         const double* ps = pl;
         if (!remove_mean) {
             project_mean(pl, pp);
             ps = pp;
         }
         stokes(prm, zero, ps, nullptr, ul, false, nullptr);
+        if (slot) copy(ul, slot + n, 3 * n);
         dev_normal_component(P, ul, out, s);
         dev_axpby(1.0, y, -1.0, out, out, n, s);
         tol_local = tl_save;
         loose32 = l_save;
     };
     auto finish = [&]() {
-        darcy(prm, v, p, false, r1, remove_mean);
+        if (image) {
+            copy(img, p, n);
+            copy(img + n, u, 3 * n);
+        }
+        darcy(prm, v, p, image, r1, remove_mean);
+        if (image) {  // keep the pre-mean-removal solution for a correction cycle
+            copy(p, img, n);
+            dev_add_scaled_scalar(img, P.scal + kScalMean, 1.0 / P.area, n, s);
+        }
         const double* ps = p;
         if (!remove_mean) {
             project_mean(p, pp);
             ps = pp;
         }
-        stokes(prm, U, ps, fx, u, false, r2);
+        stokes(prm, U, ps, fx, u, image, r2);
+        if (image) copy(u, img + n, 3 * n);
     };
     GmresOut g = gmres(outer, op, t0, v, n, false, tol, o.restart, o.maxit_ddm);
     info.ddm_iters += g.iters;
@@ -466,6 +501,8 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
         finish();
     }
     if (!conv && !corr) converged = false;
+    outer.W2 = nullptr;
+    outer.x2 = nullptr;
 }
 
 // out = p - (sum_j w_j p_j / |S|)
