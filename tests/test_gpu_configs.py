@@ -1,4 +1,10 @@
-"""The benchmark configurations beyond the unit sphere, on the GPU.
+"""The benchmark configurations beyond the default solve, on the GPU.
+
+* The porous unit sphere at h = 1/32 over K in {1, 1e-2, 1e-4} x alpha in
+  {0.1, 1, 10} (slip beta = alpha mu / sqrt(K) from 0.1 to 1000): FP64 and
+  mixed ddm_solve against the closed-form drag and each other (restart 1000:
+  for beta >= 100 the implicit-slip Stokes operator is indefinite and only a
+  long Krylov space converges).
 
 * Ellipsoid x^2 + y^2/0.64 + z^2/0.36 = 1 and a sphere radially perturbed by
   real harmonics of degree <= 4 (seeded N(0, 0.05^2) coefficients), h = 1/64,
@@ -25,7 +31,7 @@ import torch
 
 from gpu_check import check_all_layers, dev
 from oracle import oracle as O
-from workloads import fields, surfaces
+from workloads import exact, fields, surfaces
 
 pytestmark = pytest.mark.gpu
 
@@ -37,6 +43,36 @@ def sd():
     import paper_2110_10749_amd as sd
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
     return sd
+
+
+@pytest.fixture(scope="module")
+def sphere32(sd):
+    S = surfaces.sphere(1.0 / 32)
+    return S, sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / 32, max_restart=1000)
+
+
+@pytest.mark.parametrize("alpha", [0.1, 1.0, 10.0])
+@pytest.mark.parametrize("K", [1.0, 1e-2, 1e-4])
+def test_sphere_parameter_grid_h32(sd, sphere32, K, alpha):
+    S, plan = sphere32
+    E = [0.0, 0.0, 1.0]
+    De = exact.bjs_drag(K=K, beta=alpha / math.sqrt(K))
+    out = {}
+    for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
+        p, u, D, info = sd.ddm_solve(plan, 1.0, K, alpha, E, None,
+                                     opts=dict(prec=prec, restart=1000, maxit_gmres=6000))
+        torch.cuda.synchronize()
+        print(f"K={K:g} alpha={alpha:g} {prec}: drag {D[2]:.10f} exact {De:.10f} rel {abs(D[2] - De) / De:.1e} "
+              f"ddm {info['ddm_iters']} gmres {info['gmres_iters']} {time.perf_counter() - t0:.1f} s", flush=True)
+        assert info["converged"]
+        assert abs(D[2] - De) / De < 1e-5  # discretisation error at h = 1/32 (1.2e-6 at K = 1)
+        out[prec] = (host(p), host(u), D[2])
+    assert abs(out["mixed"][2] - out["fp64"][2]) < 1e-8 * abs(out["fp64"][2])
+    # both solves stop at the same tolerances (local 1e-10, interface 1e-8); p and u
+    # differ by those times the condition number, ~1e3-1e4 for beta >= 100
+    tol_up = 1e-6 if alpha / math.sqrt(K) < 50 else 1e-4
+    assert rel(out["mixed"][1], out["fp64"][1]) < tol_up and rel(out["mixed"][0], out["fp64"][0]) < tol_up
 
 
 def make_surface(kind, h):

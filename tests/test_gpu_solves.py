@@ -177,7 +177,7 @@ def test_plans_are_independent_and_reusable(sd):
     assert np.array_equal(r1, r1b)  # deterministic, bitwise
 
 
-@pytest.mark.parametrize("mode", ["refine", "relaxed"])
+@pytest.mark.parametrize("mode", ["refine", "coupled", "relaxed"])
 @pytest.mark.parametrize("inv_h,K,alpha", [(32, 1.0, 0.1), (32, 1e-2, 1.0), (16, 1e-4, 0.1)])
 def test_mixed_matches_fp64_at_solver_tolerances(sd, inv_h, K, alpha, mode):
     # default tolerances (local 1e-10, interface 1e-8): the mixed solve (float
