@@ -171,16 +171,19 @@ __device__ __forceinline__ double src_weight(const KArgs& a, int64_t j) {
 // into a record of R elements of T.  The pair kernels read the records at
 // wave-uniform addresses, so they arrive through the scalar cache in SGPRs
 // and enter the vector ALU as scalar operands: no LDS, no barriers.
-// U records (a power of two, at most 256 bytes) are read per unrolled step.
+// U records (a power of two, at most 128 bytes) are read per unrolled step.
 template <typename T, int R>
 struct alignas(16) Record {
     T v[R];
 };
 
+// records per unrolled step: the largest power of two within 128 bytes (2 for
+// the float Stokes matvec, 1 for the double one); 256 and 512 bytes measured
+// 5% and 8% slower on the whole mixed solve
 template <typename T, int R>
 __host__ __device__ constexpr int unroll_of() {
-    int u = 1;  // largest power of two with u records in 256 bytes
-    while (2 * u * R * (int)sizeof(T) <= 256) u *= 2;
+    int u = 1;
+    while (2 * u * R * (int)sizeof(T) <= 128) u *= 2;
     return u;
 }
 
