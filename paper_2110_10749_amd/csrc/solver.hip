@@ -681,8 +681,9 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
         d.out = mneg[c];
         launch_stokes_pass(P, d, s);
     }
-    // transposed operators
-    auto opDT = [&](const double* l, double* out) {
+    // transposed operators (m32: float pairs for the transposed sums; the
+    // diagonal terms dl1 and M above stay double)
+    auto opDT = [&](const double* l, double* out, bool m32) {
         PassDesc d;
         d.dl = true;
         d.target_normal = true;
@@ -691,11 +692,12 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
         d.c_dl = -1.0 / (4.0 * kPi);
         d.dl_dens = l;
         d.out = tA;
+        d.mixed = m32;
         launch_laplace_pass(P, d, s);
         dev_dot(P, l, nullptr, n, P.scal + kScalCompD, s);
         dev_adj_darcy(P, tA, l, dl1, P.scal + kScalCompD, out, s);
     };
-    auto opST = [&](const double* l, double* out) {
+    auto opST = [&](const double* l, double* out, bool m32) {
         PassDesc d;
         d.dl = true;
         d.target_normal = true;
@@ -704,6 +706,7 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
         d.c_dl = 3.0 / (4.0 * kPi);
         d.dl_dens = l;
         d.out = tB;
+        d.mixed = m32;
         launch_stokes_pass(P, d, s);
         if (beta != 0.0) {
             PassDesc e2;
@@ -712,16 +715,23 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
             e2.c_sl = 1.0 / (8.0 * kPi * mu);
             e2.sl_dens = l;
             e2.out = tC;
+            e2.mixed = m32;
             launch_stokes_pass(P, e2, s);
         }
         dev_normal_component(P, l, tD, s);
         dev_dot(P, tD, nullptr, n, P.scal + kScalCompS, s);
         dev_adj_stokes(P, l, m0, m1, m2, tB, beta != 0.0 ? tC : nullptr, P.scal + kScalCompS, beta, out, s);
     };
-    auto solve_T = [&](const std::function<void(const double*, double*)>& op, const double* b, double* x, int64_t L) {
-        GmresOut g = gmres(inner, [&](const double* in, double* out, bool, double) { op(in, out); }, b, x, L,
-                           false, o.tol_gmres, o.restart, o.maxit_gmres);
+    // transposed local solves: double pairs, or with float pairs the relaxed
+    // GMRES of the forward solves (float products below tol_mixed, double
+    // true residuals decide convergence)
+    const bool mixed = o.prec == SDBIE_MIXED;
+    auto solve_T = [&](const std::function<void(const double*, double*, bool)>& op, const double* b, double* x,
+                       int64_t L) {
+        GmresOut g = gmres(inner, [&](const double* in, double* out, bool m32, double) { op(in, out, m32); }, b, x,
+                           L, false, o.tol_gmres, o.restart, o.maxit_gmres, mixed ? o.tol_mixed : 0.0);
         info.gmres_iters += g.iters;
+        if (mixed) info.refine_steps += g.checks;
         info.relres = g.relres;
         if (!g.conv) converged = false;
     };

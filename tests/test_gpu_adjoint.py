@@ -92,6 +92,27 @@ def test_adjoint_matches_central_differences(sd):
         assert abs(ad - fd) < 1e-5 * max(abs(fd), 1e-3)
 
 
+@pytest.mark.parametrize("K,alpha", [(1e-2, 1.0), (1.0, 0.3)])
+def test_mixed_adjoint_matches_fp64(sd, K, alpha):
+    # the transposed local solves with float pairs (relaxed GMRES, double true
+    # residuals) give the gradient of the double path at the default tolerances
+    S = surfaces.perturbed_sphere(1.0 / 16, lmax=4, sigma=0.05, seed=4)
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / 16)
+    U = fields.unit_vector(7)
+    e = fields.unit_vector(8)
+    res = {}
+    for prec in ("fp64", "mixed"):
+        p, u, D, info = sd.ddm_solve(plan, 1.0, K, alpha, U, None, opts=dict(prec=prec))
+        gx, gK, ga, ainfo = sd.ddm_adjoint(plan, 1.0, K, alpha, U, p, u, e, None, opts=dict(prec=prec))
+        print(prec, ainfo, gK, ga, flush=True)
+        assert info["converged"] and ainfo["converged"]
+        res[prec] = (gx.cpu().numpy(), gK, ga, ainfo)
+    assert res["mixed"][3]["applies_mixed"] > 0
+    assert rel(res["mixed"][0], res["fp64"][0]) < 1e-7
+    assert abs(res["mixed"][1] - res["fp64"][1]) < 1e-7 * abs(res["fp64"][1])
+    assert abs(res["mixed"][2] - res["fp64"][2]) < 1e-7 * abs(res["fp64"][2])
+
+
 def test_autograd_function(sd):
     S = surfaces.sphere(1.0 / 8)
     x = dev(S.x).requires_grad_(True)
