@@ -37,11 +37,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP32 without packed instructions (this build disables packed-FP32 selection):
-# 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s (an FMA-chain probe reaches 77.8)
-PEAK_FP32 = 256 * 64 * 2 * 2.4e9 / 1e12
-PEAK_FP32_PUBLISHED = 157.3                           # needs packed FP32 (v_pk_fma_f32)
-PEAK_FP64 = 78.6                                      # published FP64 vector peak (probe: 77.1)
+# Published vector peaks.  FP32: 256 CU x 128 lanes x 2 flop x 2.4 GHz = 157.3
+# TFLOP/s, reached without packed instructions (this build disables them):
+# an FP32 VALU instruction whose operands are all VGPRs issues every 2 cycles
+# per wave64 (probe: 2.05-2.5), one that reads an SGPR every 4 cycles.
+# FP64: 78.6 TFLOP/s (probe: 4.3 cycles per wave64 FMA).
+PEAK_FP32 = 157.3
+PEAK_FP64 = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -208,9 +210,8 @@ def main() -> int:
                 "frac": achieved / peak, "traffic": measured_traffic(dom["name"], S.N),
                 "kernel": dom["name"], "avg_ms": avg_ms, "launches_per_step": dom["launches"] / args.steps,
                 "flops_per_pair": dom["flops_per_pair"], "pairs_per_launch": pairs_per_launch,
-                "peak_basis": ("fp32 without packed instructions: 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz"
-                               if is32 else "published fp64 vector peak"),
-                "frac_of_published_fp32_peak": achieved / PEAK_FP32_PUBLISHED if is32 else None}
+                "peak_basis": ("published fp32 vector peak (VGPR-operand VALU at 2 cycles per wave64 "
+                               "instruction, no packed instructions)" if is32 else "published fp64 vector peak")}
     kernel_ms_total = sum(s["ms"] for s in stats)
 
     result = {

@@ -33,6 +33,17 @@ constexpr int kMaxSplit = 64;    // source splits of one pair pass
 constexpr int64_t kMaxNodes = (int64_t)1 << 23;  // the tile-pair masks grow as (n/256)^2 bytes
 constexpr int kNearUnit = 64;    // sources per work unit of the near-field kernel
 constexpr int kRecBytes = 128;   // largest per-source record of a pair pass
+// bytes of source records per unrolled step of the pair loops
+#ifndef SDBIE_GROUP_BYTES_F32
+#define SDBIE_GROUP_BYTES_F32 128
+#endif
+// float far-field records through LDS (1) or the scalar cache (0)
+#ifndef SDBIE_FAR_LDS
+#define SDBIE_FAR_LDS 1
+#endif
+#ifndef SDBIE_GROUP_BYTES_F64
+#define SDBIE_GROUP_BYTES_F64 128
+#endif
 constexpr int kMaxRestart = 1000; // largest GMRES restart length of a plan
 #ifndef SDBIE_SPLIT_TARGET
 #define SDBIE_SPLIT_TARGET 8192      // pair-kernel grids aim for at least this many blocks (fills the 8 waves per SIMD about 4 times at the benchmark size)

@@ -13,8 +13,10 @@
 // branch is taken by few waves); the source range is cut into `nsplit` equal
 // chunks, one per block, with split = blockIdx.x % nsplit so that the
 // round-robin dispatch over the 8 XCDs gives each XCD a fixed subset of the
-// source chunks (and its L2 only those sources).  Source records are read at
-// wave-uniform addresses, through the scalar cache into SGPRs.
+// source chunks (and its L2 only those sources).  The float far-field kernel
+// stages source tiles in LDS and reads them back as broadcast loads into
+// VGPRs; the other kernels read source records at wave-uniform addresses
+// through the scalar cache into SGPRs.
 // Partial sums per split go to a scratch array and an epilogue kernel adds
 // them in a fixed order (no atomics: results are bitwise reproducible).
 //
@@ -34,6 +36,12 @@
 namespace sdbie {
 namespace {
 
+// Source records are read through a constant-address-space pointer: they do
+// not change during a pass, and loads from that space at wave-uniform
+// addresses always become scalar loads into SGPRs.
+template <typename T>
+using src_ptr = const __attribute__((address_space(4))) T*;
+
 constexpr double kTwoOverSqrtPi = 1.12837916709551257389615890312154517;  // 2/sqrt(pi)
 constexpr double kPiD = 3.14159265358979323846;
 
@@ -51,8 +59,7 @@ __device__ __forceinline__ float rsq_pos(float v) { return __builtin_amdgcn_rsqf
 // far-field pairs never reach r = 0; near-field pairs do (the self pair)
 template <bool NEAR, typename T>
 __device__ __forceinline__ T rsq_pair(T v) { return NEAR ? rsq(v) : rsq_pos(v); }
-__device__ __forceinline__ double exp_t(double v) { return exp(v); }
-__device__ __forceinline__ float exp_t(float v) { return __expf(v); }
+__device__ __forceinline__ float exp_neg(float x) { return __expf(-x); }
 // 1/v for v in [1, 4] (no special cases): hardware estimate, two Newton steps in double
 __device__ __forceinline__ double rcp_t(double v) {
     double y = __builtin_amdgcn_rcp(v);
@@ -69,7 +76,48 @@ __device__ __forceinline__ T horner(const T (&c)[N], T x) {
     return a;
 }
 
-__device__ __forceinline__ double erfcx_fit(double t) { return horner(kERFCX_F64, t); }
+// Double polynomials: the coefficients are read at the point of use through
+// the scalar cache and enter each Horner step as the SGPR addend of one
+// v_fma_f64.  Left to itself the compiler keeps every double coefficient of
+// the near-field code in VGPRs (about a hundred registers, which caps the
+// double near-field kernels at two or three waves per SIMD) and copies each
+// one into the accumulator of a v_fmac_f64 with a v_mov_b64, two
+// instructions per step.  The empty asm makes the table address opaque, so
+// the loads stay at the point of use instead of being hoisted out of the
+// source loop into registers.
+typedef const __attribute__((address_space(4))) double cdouble;
+template <int N>
+__device__ __forceinline__ double horner_s(const double (&tab)[N], double x) {
+    cdouble* c = (cdouble*)tab;
+    asm volatile("" : "+s"(c));
+    double a = c[N - 1];
+#pragma unroll
+    for (int i = N - 2; i >= 0; --i) {
+        double r;
+        asm("v_fma_f64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(x), "s"(c[i]));
+        a = r;
+    }
+    return a;
+}
+
+// e^{-x} in double for 0 <= x <= 700: Cody-Waite reduction x = n ln2 + r
+// (ln2 split in a double and its remainder, both products taken by fma),
+// |r| <= ln2/2, then the degree-13 Taylor polynomial of e^{-r} (truncation
+// below 5e-18 relative) and a power-of-two scale.
+__device__ static constexpr double kExpTaylor[14] = {
+    1.0, 1.0, 1.0 / 2, 1.0 / 6, 1.0 / 24, 1.0 / 120, 1.0 / 720, 1.0 / 5040, 1.0 / 40320, 1.0 / 362880,
+    1.0 / 3628800, 1.0 / 39916800, 1.0 / 479001600, 1.0 / 6227020800.0};
+__device__ __forceinline__ double exp_neg(double x) {
+    constexpr double kLog2e = 1.44269504088896340736;
+    constexpr double kLn2Hi = 0.693147180559945309417;       // ln 2 rounded to double
+    constexpr double kLn2Lo = 2.319046813846299558e-17;      // ln 2 - kLn2Hi
+    const double n = rint(x * kLog2e);
+    double r = fma(-n, kLn2Hi, x);
+    r = fma(-n, kLn2Lo, r);
+    return ldexp(horner_s(kExpTaylor, -r), -(int)n);
+}
+
+__device__ __forceinline__ double erfcx_fit(double t) { return horner_s(kERFCX_F64, t); }
 __device__ __forceinline__ float erfcx_fit(float t) { return horner(kERFCX_F32, t); }
 // erf(rho) for rho between the series branch point and the far cutoff, given
 // E = exp(-rho^2): erf = 1 - E erfcx(rho), with erfcx from its fitted
@@ -79,10 +127,10 @@ __device__ __forceinline__ T erf_near(T rho, T E) {
     const T t = rcp_t(fma(T(SDBIE_ERFCX_P), rho, T(1)));
     return fma(-E, erfcx_fit(t), T(1));
 }
-__device__ __forceinline__ double ser_F1(double x) { return horner(kF1_F64, x); }
-__device__ __forceinline__ double ser_F2(double x) { return horner(kF2_F64, x); }
-__device__ __forceinline__ double ser_F3(double x) { return horner(kF3_F64, x); }
-__device__ __forceinline__ double ser_F4(double x) { return horner(kF4_F64, x); }
+__device__ __forceinline__ double ser_F1(double x) { return horner_s(kF1_F64, x); }
+__device__ __forceinline__ double ser_F2(double x) { return horner_s(kF2_F64, x); }
+__device__ __forceinline__ double ser_F3(double x) { return horner_s(kF3_F64, x); }
+__device__ __forceinline__ double ser_F4(double x) { return horner_s(kF4_F64, x); }
 __device__ __forceinline__ float ser_F1(float x) { return horner(kF1_F32, x); }
 __device__ __forceinline__ float ser_F2(float x) { return horner(kF2_F32, x); }
 __device__ __forceinline__ float ser_F3(float x) { return horner(kF3_F32, x); }
@@ -114,7 +162,7 @@ __device__ __forceinline__ void near_factors(T r2, T inv_r, T id, T id2, T& k1, 
         if (K4) k4 = ser_F4(x) * id3 * id2;
     } else {
         const T rho = r2 * inv_r * id;
-        const T E = exp_t(-x);
+        const T E = exp_neg(x);
         const T ef = erf_near(rho, E);
         const T cE = T(kTwoOverSqrtPi) * rho * E;
         const T ir2 = inv_r * inv_r;
@@ -178,12 +226,12 @@ struct alignas(16) Record {
 };
 
 // records per unrolled step: the largest power of two within 128 bytes (2 for
-// the float Stokes matvec, 1 for the double one); 256 and 512 bytes measured
-// 5% and 8% slower on the whole mixed solve
+// the float Stokes matvec, 1 for the double one); for the double kernels 256
+// and 512 bytes measured 1% faster and 3% slower
 template <typename T, int R>
 __host__ __device__ constexpr int unroll_of() {
     int u = 1;
-    while (2 * u * R * (int)sizeof(T) <= 128) u *= 2;
+    while (2 * u * R * (int)sizeof(T) <= (sizeof(T) == 8 ? SDBIE_GROUP_BYTES_F64 : SDBIE_GROUP_BYTES_F32)) u *= 2;
     return u;
 }
 
@@ -221,8 +269,8 @@ struct LaplaceOp {
         zi = load_x<T>(a, 2, i);
         qi = (DL && SUB) ? T(dens_at(a.dl_dens, a.n, 0, i)) : T(0);
     }
-    template <bool NEAR>
-    __device__ __forceinline__ void pair(const T* r, T id, T id2, T rc2) {
+    template <bool NEAR, class P>
+    __device__ __forceinline__ void pair(P r, T id, T id2, T rc2) {
         const T dx = xi - r[0], dy = yi - r[1], dz = zi - r[2];
         const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const T inv_r = rsq_pair<NEAR>(r2);
@@ -316,8 +364,8 @@ struct StokesOp {
             uiz = T(dens_at(tg, a.n, 2, i));
         }
     }
-    template <bool NEAR>
-    __device__ __forceinline__ void pair(const T* r, T id, T id2, T rc2) {
+    template <bool NEAR, class P>
+    __device__ __forceinline__ void pair(P r, T id, T id2, T rc2) {
         const T dx = xi - r[0], dy = yi - r[1], dz = zi - r[2];
         const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const T inv_r = rsq_pair<NEAR>(r2);
@@ -384,8 +432,8 @@ struct LaplaceTNOp {
         nyi = T(a.nrm[a.npad + i]);
         nzi = T(a.nrm[2 * a.npad + i]);
     }
-    template <bool NEAR>
-    __device__ __forceinline__ void pair(const T* r, T id, T id2, T rc2) {
+    template <bool NEAR, class P>
+    __device__ __forceinline__ void pair(P r, T id, T id2, T rc2) {
         const T dx = xi - r[0], dy = yi - r[1], dz = zi - r[2];
         const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const T inv_r = rsq_pair<NEAR>(r2);
@@ -429,8 +477,8 @@ struct StokesTNOp {
         nyi = T(a.nrm[a.npad + i]);
         nzi = T(a.nrm[2 * a.npad + i]);
     }
-    template <bool NEAR>
-    __device__ __forceinline__ void pair(const T* r, T id, T id2, T rc2) {
+    template <bool NEAR, class P>
+    __device__ __forceinline__ void pair(P r, T id, T id2, T rc2) {
         const T dx = xi - r[0], dy = yi - r[1], dz = zi - r[2];
         const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const T inv_r = rsq_pair<NEAR>(r2);
@@ -465,11 +513,11 @@ __device__ __forceinline__ void near_G(double r2, double inv_r, double id, doubl
     const double x = r2 * id2;
     const double id5 = id * id2 * id2;
     if (x < Consts<double>::rho_s2) {
-        g2 = horner(kG2_F64, x) * id5;
-        g4 = horner(kG4_F64, x) * id5 * id2;
+        g2 = horner_s(kG2_F64, x) * id5;
+        g4 = horner_s(kG4_F64, x) * id5 * id2;
     } else {
         const double rho = r2 * inv_r * id;
-        const double E = exp(-x);
+        const double E = exp_neg(x);
         const double ef = erf_near(rho, E);
         const double cE = kTwoOverSqrtPi * rho * E;
         const double ir2 = inv_r * inv_r;
@@ -586,7 +634,7 @@ struct GradOp {
         else t = load_gtgt(a, i);
     }
     template <bool NEAR>
-    __device__ __forceinline__ void pair(const double* r, double id, double id2, double rc2) {
+    __device__ __forceinline__ void pair(src_ptr<double> r, double id, double id2, double rc2) {
         if (SWAP) {
             GTgt q;
             q.x = r[0]; q.y = r[1]; q.z = r[2]; q.p = r[3];
@@ -626,7 +674,7 @@ __global__ __launch_bounds__(256) void pack_sources(KArgs a) {
 
 // NU consecutive records starting at r (wave-uniform address)
 template <class Op, typename T, bool NEAR, int NU>
-__device__ __forceinline__ void pair_group(Op& op, const T* r, T id, T id2, T rc2) {
+__device__ __forceinline__ void pair_group(Op& op, src_ptr<T> r, T id, T id2, T rc2) {
 #pragma unroll
     for (int u = 0; u < NU; ++u) op.template pair<NEAR>(r + u * Op::R, id, id2, rc2);
 }
@@ -646,14 +694,79 @@ __global__ __launch_bounds__(kTPB) void far_pairs(KArgs a) {
     const int t0 = split * a.tiles_per_split;
     const int t1 = t0 + a.tiles_per_split < a.ntiles ? t0 + a.tiles_per_split : a.ntiles;
     const uint8_t* row = a.mask + (int64_t)b * a.ntiles;
-    const T* rec = static_cast<const T*>(a.rec);
+    const src_ptr<T> rec = (src_ptr<T>)a.rec;
     for (int t = t0; t < t1; ++t) {
         if (row[t]) continue;  // uniform
-        const T* rt = rec + (int64_t)t * kTile * Op::R;
+        const src_ptr<T> rt = rec + (int64_t)t * kTile * Op::R;
 #pragma unroll 1
         for (int jj = 0; jj < kTile; jj += Op::U)
             pair_group<Op, T, false, Op::U>(op, rt + jj * Op::R, id, id2, rc2);
         op.flush();
+    }
+    if (i < a.n) op.store(a, split, i);
+}
+
+// Far-field pass in float: the block stages each source tile in LDS (one
+// record per thread, coalesced; the next tile is loaded into registers while
+// the current one is summed) and every wave reads the records back as
+// broadcast LDS loads into VGPRs.  Float VALU instructions whose operands
+// are all VGPRs issue at twice the rate of those that read an SGPR, so this
+// form beats scalar-cache records once half the pair's instructions would
+// read one.
+template <class Op>
+__global__ __launch_bounds__(kTPB) void far_pairs_lds(KArgs a) {
+    using T = float;
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    constexpr int R = Op::R, Q = R / 4;
+    static_assert(R % 4 == 0, "records of whole float4s");
+    static_assert(kTile == kTPB, "one record per thread when staging a tile");
+    static_assert(kTile % Op::U == 0, "unroll must divide the tile");
+    __shared__ f4 tile[kTile * Q];
+    const int split = blockIdx.x % a.nsplit;
+    const int b = blockIdx.x / a.nsplit;
+    const int64_t i = (int64_t)b * kTPB + threadIdx.x;  // < npad
+    Op op;
+    op.init(a, i);
+    const T id = T(a.inv_delta), id2 = id * id, rc2 = T(a.rc2);
+    const int t0 = split * a.tiles_per_split;
+    const int t1 = t0 + a.tiles_per_split < a.ntiles ? t0 + a.tiles_per_split : a.ntiles;
+    const uint8_t* row = a.mask + (int64_t)b * a.ntiles;
+    const f4* rec = static_cast<const f4*>(a.rec);
+    int t = t0;
+    while (t < t1 && row[t]) ++t;  // uniform
+    f4 pf[Q];
+    const f4* g = rec + (int64_t)(t < t1 ? t : 0) * kTile * Q + threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < Q; ++c) pf[c] = g[c * kTPB];
+    while (t < t1) {
+        __syncthreads();  // every wave is done with the previous tile
+#pragma unroll
+        for (int c = 0; c < Q; ++c) tile[threadIdx.x + c * kTPB] = pf[c];
+        __syncthreads();
+        int tn = t + 1;
+        while (tn < t1 && row[tn]) ++tn;
+        // the next tile's records (this one's again after the last)
+        g = rec + (int64_t)(tn < t1 ? tn : t) * kTile * Q + threadIdx.x;
+#pragma unroll
+        for (int c = 0; c < Q; ++c) pf[c] = g[c * kTPB];
+#pragma unroll 1
+        for (int jj = 0; jj < kTile; jj += Op::U) {
+#pragma unroll
+            for (int u = 0; u < Op::U; ++u) {
+                T r[R];
+#pragma unroll
+                for (int c = 0; c < Q; ++c) {
+                    const f4 v = tile[(jj + u) * Q + c];
+                    r[4 * c] = v[0];
+                    r[4 * c + 1] = v[1];
+                    r[4 * c + 2] = v[2];
+                    r[4 * c + 3] = v[3];
+                }
+                op.template pair<false>(static_cast<const T*>(r), id, id2, rc2);
+            }
+        }
+        op.flush();
+        t = tn;
     }
     if (i < a.n) op.store(a, split, i);
 }
@@ -691,7 +804,7 @@ __global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
         wb[2 * c + 1] = hi;
     }
     const uint8_t* row = a.mask + (int64_t)b * a.ntiles;
-    const T* rec = static_cast<const T*>(a.rec);
+    const src_ptr<T> rec = (src_ptr<T>)a.rec;
     constexpr int kUnits = kTile / kNearUnit;
     int rank = 0;
     const int lane = threadIdx.x & 63;
@@ -704,10 +817,10 @@ __global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
             for (int q = 0; q < kUnits; ++q) {
                 if ((rank * kUnits + q) % a.nsplit != split) continue;
                 const int64_t u0 = (int64_t)t * kTile + q * kNearUnit;
-                const T* ru = rec + u0 * Op::R;
+                const src_ptr<T> ru = rec + u0 * Op::R;
                 bool far_unit = wave_full && u0 + kNearUnit <= a.n;
                 if (far_unit) {
-                    const double* ub = a.uboxes + (u0 / kNearUnit) * 6;
+                    const src_ptr<double> ub = (src_ptr<double>)a.uboxes + (u0 / kNearUnit) * 6;
                     double d2 = 0.0;
                     for (int c = 0; c < 3; ++c) {
                         const double gap = fmax(0.0, fmax(wb[2 * c] - ub[2 * c + 1], ub[2 * c] - wb[2 * c + 1]));
@@ -802,7 +915,10 @@ void launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int fami
     const dim3 grid((unsigned)((int64_t)a.ntiles * a.nsplit));
     {
         ProfScope prof(prof_variant(family, mixed, code, 0), all - near, st);
-        hipLaunchKernelGGL((far_pairs<Op, T>), grid, dim3(kTPB), 0, st, a);
+        if constexpr (sizeof(T) == 4 && SDBIE_FAR_LDS)
+            hipLaunchKernelGGL((far_pairs_lds<Op>), grid, dim3(kTPB), 0, st, a);
+        else
+            hipLaunchKernelGGL((far_pairs<Op, T>), grid, dim3(kTPB), 0, st, a);
         SDBIE_LAUNCHED();
     }
     {
