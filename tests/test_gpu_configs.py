@@ -1,10 +1,10 @@
 """The benchmark configurations beyond the default solve, on the GPU.
 
-* The porous unit sphere at h = 1/32 over K in {1, 1e-2, 1e-4} x alpha in
-  {0.1, 1, 10} (slip beta = alpha mu / sqrt(K) from 0.1 to 1000): FP64 and
-  mixed ddm_solve against the closed-form drag and each other (restart 1000:
-  for beta >= 100 the implicit-slip Stokes operator is indefinite and only a
-  long Krylov space converges).
+* The porous unit sphere at h = 1/32 and h = 1/64 over K in {1, 1e-2, 1e-4} x
+  alpha in {0.1, 1, 10} (slip beta = alpha mu / sqrt(K) from 0.1 to 1000):
+  FP64 and mixed ddm_solve against the closed-form drag and each other
+  (restart 1000: for beta >= 100 the implicit-slip Stokes operator is
+  indefinite and only a long Krylov space converges).
 
 * Ellipsoid x^2 + y^2/0.64 + z^2/0.36 = 1 and a sphere radially perturbed by
   real harmonics of degree <= 4 (seeded N(0, 0.05^2) coefficients), h = 1/64,
@@ -16,7 +16,7 @@
 * The gradient of drag on the perturbed sphere with respect to log K, alpha
   and 20 seeded node-coordinate directions against central differences of the
   FP64 forward solve (step 1e-6, tight tolerances): at h = 1/32 always, at
-  h = 1/64 (the configuration's size, ~8 minutes) with SDBIE_LONG_TESTS=1.
+  h = 1/64 (the configuration's size, about 6.5 minutes) with SDBIE_LONG_TESTS=1.
 * The large perturbed sphere (degree <= 8, h = 1/128, N = 351866), K = 1e-3,
   alpha = 1: sampled rows, and local Darcy and Stokes solves in both
   precisions.
@@ -71,6 +71,35 @@ def test_sphere_parameter_grid_h32(sd, sphere32, K, alpha):
     assert abs(out["mixed"][2] - out["fp64"][2]) < 1e-8 * abs(out["fp64"][2])
     # both solves stop at the same tolerances (local 1e-10, interface 1e-8); p and u
     # differ by those times the condition number, ~1e3-1e4 for beta >= 100
+    tol_up = 1e-6 if alpha / math.sqrt(K) < 50 else 1e-4
+    assert rel(out["mixed"][1], out["fp64"][1]) < tol_up and rel(out["mixed"][0], out["fp64"][0]) < tol_up
+
+
+@pytest.fixture(scope="module")
+def sphere64(sd):
+    S = surfaces.sphere(1.0 / 64)
+    return S, sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / 64, max_restart=1000)
+
+
+@pytest.mark.parametrize("alpha", [0.1, 1.0, 10.0])
+@pytest.mark.parametrize("K", [1.0, 1e-2, 1e-4])
+def test_sphere_parameter_grid_h64(sd, sphere64, K, alpha):
+    # the configuration's size (N = 68166); the whole grid takes about 40 s
+    S, plan = sphere64
+    E = [0.0, 0.0, 1.0]
+    De = exact.bjs_drag(K=K, beta=alpha / math.sqrt(K))
+    out = {}
+    for prec in ("fp64", "mixed"):
+        t0 = time.perf_counter()
+        p, u, D, info = sd.ddm_solve(plan, 1.0, K, alpha, E, None,
+                                     opts=dict(prec=prec, restart=1000, maxit_gmres=6000))
+        torch.cuda.synchronize()
+        print(f"K={K:g} alpha={alpha:g} {prec}: drag {D[2]:.10f} exact {De:.10f} rel {abs(D[2] - De) / De:.1e} "
+              f"ddm {info['ddm_iters']} gmres {info['gmres_iters']} {time.perf_counter() - t0:.1f} s", flush=True)
+        assert info["converged"]
+        assert abs(D[2] - De) / De < 1e-7  # discretisation error at h = 1/64: measured <= 3e-9
+        out[prec] = (host(p), host(u), D[2])
+    assert abs(out["mixed"][2] - out["fp64"][2]) < 1e-8 * abs(out["fp64"][2])
     tol_up = 1e-6 if alpha / math.sqrt(K) < 50 else 1e-4
     assert rel(out["mixed"][1], out["fp64"][1]) < tol_up and rel(out["mixed"][0], out["fp64"][0]) < tol_up
 
@@ -151,7 +180,7 @@ LONG = os.environ.get("SDBIE_LONG_TESTS") == "1"
 
 
 @pytest.mark.parametrize("inv_h", [32, pytest.param(64, marks=pytest.mark.skipif(
-    not LONG, reason="42 tight FP64 solves at N = 71002 take ~8 minutes; set SDBIE_LONG_TESTS=1"))])
+    not LONG, reason="42 tight FP64 solves at N = 71002 take about 6.5 minutes; set SDBIE_LONG_TESTS=1"))])
 def test_adjoint_perturbed_central_differences(sd, inv_h):
     S = make_surface("perturbed", 1.0 / inv_h)
     delta = 3.0 / inv_h
