@@ -99,7 +99,9 @@ typedef struct {
     int prec;           /* sdbie_precision of the pair sums in the solves */
     double tol_mixed;   /* SDBIE_MIXED: mixed_mode 0 and 1: relative tolerance of each float-pair
                            correction solve; mixed_mode 2: relative residual below which the
-                           GMRES products switch to float pairs */
+                           GMRES products of a local solve at tol_gmres switch to float pairs (a
+                           local solve at a looser tolerance tol, an inexact interface product,
+                           switches at min(1, tol_mixed * tol / tol_gmres)) */
     int refine_max;     /* SDBIE_MIXED, mixed_mode 0 and 1: maximum refinement steps */
     int mixed_mode;     /* SDBIE_MIXED: 0 = iterative refinement of every local solve (double
                            residual, float-pair correction solves); 1 = (outer = 1 only) refinement

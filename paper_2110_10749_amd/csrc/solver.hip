@@ -245,9 +245,12 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op3, co
     const bool mixed = o.prec == SDBIE_MIXED;
     if (!mixed || o.mixed_mode == 2) {
         // double pairs, or relaxed: double pairs until the residual reaches
-        // tol_mixed, float pairs below it, double-pair true residual at the end
-        GmresOut g = gmres(inner, op, b, x, L, x_nonzero, tol, o.restart, o.maxit_gmres,
-                           mixed ? o.tol_mixed : 0.0);
+        // the switch point, float pairs below it, double-pair true residual at
+        // the end.  The error a product may carry grows with the tolerance
+        // sought, so a looser local solve switches earlier: at tol_mixed for
+        // tol_gmres, in proportion above it.
+        const double relax = mixed ? std::min(1.0, o.tol_mixed * (tol / o.tol_gmres)) : 0.0;
+        GmresOut g = gmres(inner, op, b, x, L, x_nonzero, tol, o.restart, o.maxit_gmres, relax);
         if (mixed) info.refine_steps += g.checks;
         info.gmres_iters += g.iters;
         info.relres = g.relres;
@@ -380,7 +383,11 @@ void Ctx::ddm(const sdbie_params& prm, const double U[3], const double* fx, doub
 // pairs throughout once that is at least kLooseFloat.  The final solves are
 // full-accuracy; their u.n - v is the true interface residual, and a cycle
 // on the correction equation (I - T_lin) d = u.n - v follows when it is
-// above tol.
+// above tol.  The safety factor stands for the conditioning of the interface
+// operator, which the residual bound needs and nothing here knows in
+// advance: when a cycle ends with a true residual F times the one its GMRES
+// predicted, the products were about F times too inexact, and the next cycle
+// runs its local solves with the safety factor divided by F.
 namespace {
 constexpr double kOuterSafety = 1e-3;
 constexpr double kOuterLoosest = 1e-2;
@@ -426,13 +433,14 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
         outer.x2 = img;
     }
     double tol_cyc = tol;  // relative tolerance of the current cycle
+    double safety = kOuterSafety;
     int outer_steps = 0;
     auto op = [&](const double* y, double* out, bool, double rr) {
         const int kslot = krylov_index;  // the local solves below run GMRES of their own
         const double tl_save = tol_local;
         const bool l_save = loose32;
         if (relax && rr > 0.0) {
-            const double tl = std::min(kOuterLoosest, std::max(o.tol_gmres, kOuterSafety * tol_cyc / rr));
+            const double tl = std::min(kOuterLoosest, std::max(o.tol_gmres, safety * tol_cyc / rr));
             tol_local = tl;
             loose32 = o.prec == SDBIE_MIXED && tl >= kLooseFloat;
         }
@@ -482,6 +490,7 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
     info.ddm_iters += g.iters;
     info.ddm_res = g.relres;
     bool conv = g.conv;
+    double predicted = g.relres;  // the cycle's own estimate of the relative interface residual
     finish();
     for (int cyc = 1; relax && t0n > 0.0; ++cyc) {
         // true interface residual T(v) - v = u.n - v
@@ -492,11 +501,13 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
         if (debug_level() >= 1) std::fprintf(stderr, "[sdbie] true interface residual %.3e\n", rt);
         conv = rt <= tol;
         if (conv || cyc >= kOuterCycles || info.ddm_iters >= o.maxit_ddm) break;
+        if (predicted > 0.0 && rt > 10.0 * predicted) safety = std::max(safety * predicted / rt, 1e-12);
         // correction cycle: (I - T_lin) d = u.n - v, relative tolerance tol / rt
         copy(pl, t0, n);
         tol_cyc = std::min(0.5, tol / rt);
         GmresOut gc = gmres(outer, op, t0, dv, n, false, tol_cyc, o.restart, o.maxit_ddm - info.ddm_iters);
         info.ddm_iters += gc.iters;
+        predicted = rt * gc.relres;
         dev_axpby(1.0, v, 1.0, dv, v, n, s);
         finish();
     }
