@@ -5,7 +5,8 @@
 * the closed-form solution under the paper's own BJS interface conditions;
 * the dense brute-force fixed point of the coupled system (independent of
   every iteration and tolerance);
-* the contraction factor of the relaxed D-N iteration on the n = 1 mode.
+* the contraction factor of the relaxed D-N iteration on the n = 1 mode;
+* the closed-form spectrum of the D-N map on the sphere (degrees 1-4).
 """
 import math
 
@@ -71,6 +72,33 @@ def test_relaxation_contraction_factor(sphere16):
     # higher modes decay faster; after a few iterations the n = 1 mode rules
     ratios = r[6:16] / r[5:15]
     assert np.allclose(ratios, 1.0 / 3.0, atol=1e-3)
+
+
+def test_dn_map_spectrum_closed_form(sphere16):
+    # With no slip coefficient the Stokes side has zero tangential traction.
+    # Lamb's solution (the analysis section's eqs. CA11-CA22, with zero
+    # tangential stress in place of eqs. CA16-CA17) and eq. CA7 give the linear
+    # D-N map T(v) = u.n on degree-n harmonics as
+    #   lambda_n = -(R^2/K) (n+1)(2n+1) / (2n(n+2)(2n^2+1))
+    # (lambda_1 = -1/3: the contraction factor above).  The discrete map on the
+    # zonal harmonics P_n(z) approaches it; eq. CA31's no-slip factor
+    # (n+1)/(n(n+2)(2n-1)) does not describe this coupling (2x off at n = 1).
+    from scipy.special import eval_legendre
+    g, ops = sphere16
+    K = 1e-2
+    prm = O.Params(mu=1.0, K=K, alpha=0.0)
+    bound = {1: 1e-4, 2: 1e-3, 3: 5e-3, 4: 1.5e-2}
+    for n, tol in bound.items():
+        v = eval_legendre(n, g.x[2])
+        p, _ = O.darcy_solve(ops, prm, v, tol=1e-12)
+        u, _ = O.stokes_solve(ops, prm, np.zeros(3), p, tol=1e-12)
+        Tv = (u * g.n).sum(axis=0)
+        lam = (g.w * v * Tv).sum() / (g.w * v * v).sum()
+        free = -(1.0 / K) * (n + 1) * (2 * n + 1) / (2 * n * (n + 2) * (2 * n * n + 1))
+        noslip = -(1.0 / K) * (n + 1) / (n * (n + 2) * (2 * n - 1))
+        assert abs(lam - free) < tol * abs(free)
+        if n == 1:
+            assert abs(lam - noslip) > 0.4 * abs(noslip)
 
 
 def test_table2_kappa1e2_outer_gmres(sphere16, golden):
