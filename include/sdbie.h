@@ -196,11 +196,12 @@ int ddm_solve(sdbie_plan plan, const sdbie_params* prm, const double U[3], const
  * outputs of ddm_solve for the same plan, parameters, U and f_extra; only they
  * are needed (no Krylov history).  The transposed coupled system is solved by
  * the transposed interface iteration (interface GMRES to opts->tol_ddm, local
- * GMRES to opts->tol_gmres); with opts->prec = SDBIE_MIXED the transposed
- * local solves use the relaxed scheme of the forward solves (float pairs below
- * opts->tol_mixed, double true residuals), otherwise double pairs; then one
- * position-gradient pass in double.  Returns NOT_CONVERGED if a Krylov solve
- * missed its tolerance. */
+ * GMRES to opts->tol_gmres; with opts->relax_outer the inexact interface
+ * products and true-residual correction cycles of ddm_solve); with
+ * opts->prec = SDBIE_MIXED the transposed local solves use the relaxed scheme
+ * of the forward solves (float pairs below the switch point, double true
+ * residuals), otherwise double pairs; then one position-gradient pass in
+ * double.  Returns NOT_CONVERGED if a Krylov solve missed its tolerance. */
 int ddm_adjoint(sdbie_plan plan, const sdbie_params* prm, const double U[3], const double* f_extra,
                 const double* p, const double* u, const double dJ_ddrag[3], double* dJ_dx,
                 double* dJ_dlogK, double* dJ_dalpha, const sdbie_opts* opts, sdbie_info* info,

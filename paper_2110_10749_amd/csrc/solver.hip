@@ -734,13 +734,17 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
         dev_adj_stokes(P, l, m0, m1, m2, tB, beta != 0.0 ? tC : nullptr, P.scal + kScalCompS, beta, out, s);
     };
     // transposed local solves: double pairs, or with float pairs the relaxed
-    // GMRES of the forward solves (float products below tol_mixed, double
-    // true residuals decide convergence)
+    // GMRES of the forward solves (float products below the switch point,
+    // double true residuals decide convergence).  Inside an inexact interface
+    // product they run to tl_adj, all in float pairs when l32_adj.
     const bool mixed = o.prec == SDBIE_MIXED;
+    double tl_adj = o.tol_gmres;
+    bool l32_adj = false;
     auto solve_T = [&](const std::function<void(const double*, double*, bool)>& op, const double* b, double* x,
                        int64_t L) {
+        const double relax = l32_adj ? kAllFloat : (mixed ? std::min(1.0, o.tol_mixed * (tl_adj / o.tol_gmres)) : 0.0);
         GmresOut g = gmres(inner, [&](const double* in, double* out, bool m32, double) { op(in, out, m32); }, b, x,
-                           L, false, o.tol_gmres, o.restart, o.maxit_gmres, mixed ? o.tol_mixed : 0.0);
+                           L, false, tl_adj, o.restart, o.maxit_gmres, relax);
         info.gmres_iters += g.iters;
         if (mixed) info.refine_steps += g.checks;
         info.relres = g.relres;
@@ -755,6 +759,7 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
         d.c_sl = -scale / (4.0 * kPi);
         d.sl_dens = l;
         d.out = out;
+        d.mixed = l32_adj;
         launch_laplace_pass(P, d, s);
     };
     auto VT = [&](const double* l, double* out) {
@@ -765,6 +770,7 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
         d.c_sl = 1.0 / (8.0 * kPi * mu);
         d.sl_dens = l;
         d.out = out;
+        d.mixed = l32_adj;
         launch_stokes_pass(P, d, s);
     };
     // Pi^T g = g - w (sum g)/|S|   (in place)
@@ -787,16 +793,51 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
     // t0 = T'(0)
     copy(gu, tE, 3 * n);
     chain(gp, t0);
-    auto opOuter = [&](const double* y, double* out, bool, double) {
+    // the transposed interface equation, with the inexact products and
+    // correction cycles of the forward interface GMRES (relax_outer)
+    const bool relax = o.relax_outer != 0;
+    double tol_cyc = o.tol_ddm;
+    double safety = kOuterSafety;
+    auto opOuter = [&](const double* y, double* out, bool, double rr) {
+        if (relax && rr > 0.0) {
+            tl_adj = std::min(kOuterLoosest, std::max(o.tol_gmres, safety * tol_cyc / rr));
+            l32_adj = mixed && tl_adj >= kLooseFloat;
+        }
         SLT(y, 1.0, tA);                          // S_L^T y
         dev_scalar_normal(P, tA, mu / K, tE, s);  // (mu/K) N^T S_L^T y
         chain(nullptr, x1);
         dev_axpby(1.0, y, -1.0, x1, out, n, s);
+        tl_adj = o.tol_gmres;
+        l32_adj = false;
     };
     GmresOut g = gmres(outer, opOuter, t0, lam1, n, false, o.tol_ddm, o.restart, o.maxit_ddm);
     info.ddm_iters = g.iters;
     info.ddm_res = g.relres;
-    if (!g.conv) converged = false;
+    bool conv = g.conv;
+    if (relax) {
+        // true residual t0 - (I - T'_lin) lam1 with full-accuracy local solves;
+        // correction cycles while it is above tol_ddm
+        double* rt_v = P.vec(kVecImage);
+        double* dlam = P.vec(kVecImage2);
+        const double t0n = norm(t0, n);
+        double predicted = g.relres;
+        for (int cyc = 1; t0n > 0.0; ++cyc) {
+            opOuter(lam1, rt_v, false, 0.0);
+            dev_axpby(1.0, t0, -1.0, rt_v, rt_v, n, s);
+            const double rt = norm(rt_v, n) / t0n;
+            info.ddm_res = rt;
+            if (debug_level() >= 1) std::fprintf(stderr, "[sdbie] adjoint: true interface residual %.3e\n", rt);
+            conv = rt <= o.tol_ddm;
+            if (conv || cyc >= kOuterCycles || info.ddm_iters >= o.maxit_ddm) break;
+            if (predicted > 0.0 && rt > 10.0 * predicted) safety = std::max(safety * predicted / rt, 1e-12);
+            tol_cyc = std::min(0.5, o.tol_ddm / rt);
+            GmresOut gc = gmres(outer, opOuter, rt_v, dlam, n, false, tol_cyc, o.restart, o.maxit_ddm - info.ddm_iters);
+            info.ddm_iters += gc.iters;
+            dev_axpby(1.0, lam1, 1.0, dlam, lam1, n, s);
+            predicted = rt * gc.relres;
+        }
+    }
+    if (!conv) converged = false;
     // lam2 = S^-T (gu + (mu/K) N^T S_L^T lam1)
     SLT(lam1, 1.0, tA);
     dev_scalar_normal(P, tA, mu / K, tE, s);
