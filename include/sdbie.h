@@ -114,6 +114,11 @@ typedef struct {
                            float pairs throughout once loose enough with SDBIE_MIXED; convergence
                            decided by the true interface residual of full-accuracy final solves);
                            0 = every local solve to tol_gmres */
+    int local_solver;   /* 0 = GMRES; 1 = successive approximations of eqs. (Darcy_BIEM_iter),
+                           (Stokes_BIEM_iter): x <- x + (b - A x) with the completed operator,
+                           double pairs, until the relative change ||dx|| / ||x|| <= tol_gmres
+                           (converges only while the spectral radius of I - A is below 1: no
+                           or weak slip); maxit_gmres bounds the sweeps */
 } sdbie_opts;
 
 typedef struct {
@@ -131,7 +136,7 @@ typedef struct sdbie_plan_s* sdbie_plan;
 
 /* Fill `o` with the defaults: tol_gmres 1e-10, tol_ddm 1e-8, theta 0.5,
  * maxit_gmres 500, restart 50, maxit_ddm 200, outer 1, slip 0, prec FP64,
- * tol_mixed 1e-4, refine_max 8, mixed_mode 2, relax_outer 1. */
+ * tol_mixed 1e-4, refine_max 8, mixed_mode 2, relax_outer 1, local_solver 0. */
 void sdbie_default_opts(sdbie_opts* o);
 
 /* Bytes of device workspace a plan for n nodes (1 <= n <= 2^23) and GMRES

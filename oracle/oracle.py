@@ -303,6 +303,7 @@ class Opts:
     maxit_ddm: int = 200
     outer: str = "sa"       # "sa" (relaxation, eq. (q_update)) or "gmres"
     slip: str = "implicit"  # "implicit" or "lagged" (u^{(k-1)} in the BJS condition)
+    local: str = "gmres"    # local solves: "gmres" or "sa" (successive approximations)
 
 
 @dataclass
@@ -331,7 +332,22 @@ def drag(geo: Geometry, f) -> np.ndarray:
     return (geo.w[None, :] * f).sum(axis=1)
 
 
-def darcy_solve(ops: Operators, prm: Params, v, p0=None, tol=1e-10, restart=50, maxit=500):
+def successive_approximations(matvec, b, x0=None, tol=1e-10, maxit=500):
+    """Eqs. (Darcy_BIEM_iter), (Stokes_BIEM_iter): x <- x + (b - A x), i.e.
+    x <- (I - A) x + b with A = 1/2 - H (or 1/2 - K), until the relative change
+    ||x_new - x||_2 / ||x_new||_2 is at most tol.  Returns (x, sweeps)."""
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, dtype=np.float64)
+    for m in range(1, maxit + 1):
+        d = b - matvec(x)
+        x = x + d
+        nx = np.linalg.norm(x)
+        if (np.linalg.norm(d) / nx if nx > 0 else 0.0) <= tol:
+            return x, m
+    return x, maxit
+
+
+def darcy_solve(ops: Operators, prm: Params, v, p0=None, tol=1e-10, restart=50, maxit=500, local="gmres"):
     """Eq. (Darcy_final): (1/2 - H) p = b_D, b_D = -L dp/dn, dp/dn = -(mu/K) v.
 
     v = u.n on the nodes.  Solved as Abar_D p = -S_L[g] with GMRES, then the
@@ -340,13 +356,16 @@ def darcy_solve(ops: Operators, prm: Params, v, p0=None, tol=1e-10, restart=50, 
     geo = ops.geo
     g = -(prm.mu / prm.K) * np.asarray(v, dtype=np.float64)
     b = -ops.S_L(g)
-    p, it, _ = gmres(ops.Abar_D, b, p0, tol, restart, maxit)
+    if local == "sa":
+        p, it = successive_approximations(ops.Abar_D, b, p0, tol, maxit)
+    else:
+        p, it, _ = gmres(ops.Abar_D, b, p0, tol, restart, maxit)
     p = p - (geo.w @ p) / geo.area
     return p, it
 
 
 def stokes_solve(ops: Operators, prm: Params, U, p, f_extra=None, u0=None, slip="implicit",
-                 u_prev=None, tol=1e-10, restart=50, maxit=500):
+                 u_prev=None, tol=1e-10, restart=50, maxit=500, local="gmres"):
     """Eq. (Stokes_final): (1/2 - K) u = U - M f with f of eq. (f).
 
     implicit slip: Abar_S u + V[beta P_tau u] = U - V[-p n + f_extra];
@@ -367,7 +386,10 @@ def stokes_solve(ops: Operators, prm: Params, U, p, f_extra=None, u0=None, slip=
         up = np.zeros((3, geo.N)) if u_prev is None else u_prev
         rhs = U - ops.V(traction(geo, prm, p, up, f_extra))
         mv = ops.Abar_S
-    u, it, _ = gmres(mv, rhs, u0, tol, restart, maxit)
+    if local == "sa":
+        u, it = successive_approximations(mv, rhs, u0, tol, maxit)
+    else:
+        u, it, _ = gmres(mv, rhs, u0, tol, restart, maxit)
     return u, it
 
 
@@ -384,7 +406,7 @@ def ddm_solve(ops: Operators, prm: Params, U, f_extra=None, opts: Opts | None = 
     opts = opts or Opts()
     geo = ops.geo
     info = Info()
-    kw = dict(tol=opts.tol_gmres, restart=opts.restart, maxit=opts.maxit_gmres)
+    kw = dict(tol=opts.tol_gmres, restart=opts.restart, maxit=opts.maxit_gmres, local=opts.local)
     if opts.outer == "sa":
         v = np.zeros(geo.N)
         p = np.zeros(geo.N)

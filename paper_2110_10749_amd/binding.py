@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
                 ("maxit_gmres", ctypes.c_int), ("restart", ctypes.c_int), ("maxit_ddm", ctypes.c_int),
                 ("outer", ctypes.c_int), ("slip", ctypes.c_int), ("prec", ctypes.c_int),
                 ("tol_mixed", ctypes.c_double), ("refine_max", ctypes.c_int), ("mixed_mode", ctypes.c_int),
-                ("relax_outer", ctypes.c_int)]
+                ("relax_outer", ctypes.c_int), ("local_solver", ctypes.c_int)]
 
 
 class KernelStat(ctypes.Structure):
@@ -65,7 +65,7 @@ class Info(ctypes.Structure):
 
 
 _lib = None
-ABI_VERSION = 2  # layout of the structs above (sdbie_abi_version)
+ABI_VERSION = 3  # layout of the structs above (sdbie_abi_version)
 
 
 def lib():
@@ -166,6 +166,8 @@ def default_opts(**kw) -> Opts:
             v = {"implicit": 0, "lagged": 1}[v]
         if k == "mixed_mode" and isinstance(v, str):
             v = {"refine": 0, "coupled": 1, "relaxed": 2}[v]
+        if k == "local_solver" and isinstance(v, str):
+            v = {"gmres": 0, "sa": 1}[v]
         setattr(o, k, v)
     return o
 

@@ -98,6 +98,7 @@ sdbie_opts checked_opts(const sdbie_opts* op, const Plan& P) {
     if (o.refine_max < 1) fail(SDBIE_ERR_ARG, "refine_max must be >= 1");
     if (o.mixed_mode < 0 || o.mixed_mode > 2) fail(SDBIE_ERR_ARG, "mixed_mode must be 0, 1 or 2");
     if (o.relax_outer != 0 && o.relax_outer != 1) fail(SDBIE_ERR_ARG, "relax_outer must be 0 or 1");
+    if (o.local_solver != 0 && o.local_solver != 1) fail(SDBIE_ERR_ARG, "local_solver must be 0 or 1");
     return o;
 }
 
@@ -179,6 +180,7 @@ void sdbie_default_opts(sdbie_opts* o) {
     o->refine_max = 8;
     o->mixed_mode = 2;
     o->relax_outer = 1;
+    o->local_solver = 0;
 }
 
 size_t sdbie_workspace_bytes(int64_t n, int max_restart) {
@@ -186,7 +188,7 @@ size_t sdbie_workspace_bytes(int64_t n, int max_restart) {
     return workspace_bytes(n, max_restart);
 }
 
-int sdbie_abi_version(void) { return 2; }
+int sdbie_abi_version(void) { return 3; }
 
 const char* sdbie_last_error(void) { return g_last_error.c_str(); }
 

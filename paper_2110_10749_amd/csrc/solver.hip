@@ -236,6 +236,29 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op3, co
         return;
     }
     const double tol = tol_local > 0.0 ? tol_local : o.tol_gmres;
+    if (o.local_solver == 1) {
+        // successive approximations (eqs. Darcy_BIEM_iter, Stokes_BIEM_iter)
+        // on the completed operator: x <- x + (b - A x) until the relative
+        // change is at most tol; double pairs
+        if (!x_nonzero) dev_fill(0.0, x, L, s);
+        double ch = 0.0;
+        int m = 0;
+        while (m < o.maxit_gmres) {
+            ++m;
+            op3(x, rbuf, false);
+            dev_axpby(1.0, b, -1.0, rbuf, rbuf, L, s);  // the change b - A x
+            const double dn = norm(rbuf, L);
+            dev_axpby(1.0, x, 1.0, rbuf, x, L, s);
+            const double xn = norm(x, L);
+            ch = xn > 0.0 ? dn / xn : 0.0;
+            if (!std::isfinite(ch)) throw Error(SDBIE_ERR_NONFINITE, "successive approximations diverged");
+            if (ch <= tol) break;
+        }
+        info.gmres_iters += m;
+        info.relres = ch;
+        if (ch > tol) converged = false;
+        return;
+    }
     if (loose32) {
         // a loose inexact interface product: float pairs throughout, no double check
         GmresOut g = gmres(inner, op, b, x, L, x_nonzero, tol, o.restart, o.maxit_gmres, kAllFloat);

@@ -106,6 +106,27 @@ def test_ddm_benchmark_mode_relaxation_matches_table1(sd, s16, golden):
     assert float(f"{rms(host(u) - exact.jt_velocity(S.x, E, K=1.0)):.3e}") == ref["err_u"]
 
 
+def test_table1_successive_approximations_match_oracle(sd, s16, golden):
+    # Table 1 with its own local solver (successive approximations, relative
+    # change 1e-9) and D-N relaxation: the same sweeps, iterations and fields
+    # as the oracle's, and the printed errors
+    S, geo, ops, plan = s16
+    fx = exact.jt_viscous_traction(S.x, E, K=1.0)
+    opts = dict(outer="sa", theta=0.5, tol_gmres=1e-9, tol_ddm=1e-9, local_solver="sa", maxit_gmres=1000)
+    p, u, D, info = sd.ddm_solve(plan, 1.0, 1.0, 0.0, E, dev(fx), opts=opts)
+    pr, ur, Dr, inf_r = O.ddm_solve(ops, O.Params(1.0, 1.0, 0.0), E, fx,
+                                    O.Opts(theta=0.5, tol_gmres=1e-9, tol_ddm=1e-9, local="sa", maxit_gmres=1000))
+    sweeps = sum(inf_r.gmres_darcy) + sum(inf_r.gmres_stokes)
+    print(info, inf_r.ddm_iters, sweeps, flush=True)
+    assert info["converged"] and info["ddm_iters"] == inf_r.ddm_iters
+    assert abs(info["gmres_iters"] - sweeps) <= 2  # a sweep may land either side of the threshold
+    assert rel(host(p), pr) < 1e-7 and rel(host(u), ur) < 1e-7
+    ref = golden["table1_h16"]
+    assert float(f"{rms(host(p) - exact.jt_pressure(S.x, E, K=1.0)):.3e}") == ref["err_p"]
+    assert float(f"{rms(host(u) - exact.jt_velocity(S.x, E, K=1.0)):.3e}") == ref["err_u"]
+    assert info["ddm_iters"] - 1 == ref["dn_sa_theta05"]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_ddm_physical_mode_outer_gmres(sd, s16, prec):
     # the paper's interface conditions with slip (K = 1e-2, alpha = 1: beta = 10)

@@ -60,6 +60,24 @@ def test_table1_benchmark_kappa1(sphere16, golden):
     assert counts[0.75] - 1 == ref["dn_sa_theta075"]
 
 
+def test_table1_with_successive_approximations(sphere16, golden):
+    # Table 1's own local solver: successive approximations, eqs.
+    # (Darcy_BIEM_iter), (Stokes_BIEM_iter), to a relative change of 1e-9; the
+    # D-N count and the errors are those printed (the local sweep counts depend
+    # on the stopping rule: 50..2 and 40..1 here against the printed 37-2, 26-2)
+    g, ops = sphere16
+    ref = golden["table1_h16"]
+    prm = O.Params(mu=1.0, K=1.0, alpha=0.0)
+    fx = exact.jt_viscous_traction(g.x, E, K=1.0)
+    opts = O.Opts(theta=0.5, tol_gmres=1e-9, tol_ddm=1e-9, local="sa", maxit_gmres=1000)
+    p, u, D, info = O.ddm_solve(ops, prm, E, fx, opts)
+    assert sig4(rms(p - exact.jt_pressure(g.x, E, K=1.0))) == ref["err_p"]
+    assert sig4(rms(u - exact.jt_velocity(g.x, E, K=1.0))) == ref["err_u"]
+    assert info.ddm_iters - 1 == ref["dn_sa_theta05"]
+    assert max(info.gmres_darcy) == 50 and info.gmres_darcy[-1] == 2
+    assert max(info.gmres_stokes) == 40 and info.gmres_stokes[-1] == 1
+
+
 def test_relaxation_contraction_factor(sphere16):
     # n = 1 mode factor of the free-slip D-N map: lambda_1 = -(R^2/K)/3, so the
     # relaxed iteration contracts by (1 - theta) + theta lambda_1 = 1/3 at
