@@ -119,6 +119,12 @@ typedef struct {
                            double pairs, until the relative change ||dx|| / ||x|| <= tol_gmres
                            (converges only while the spectral radius of I - A is below 1: no
                            or weak slip); maxit_gmres bounds the sweeps */
+    int recycle;        /* SDBIE_FP64: 1 = the Stokes local solves of ddm_solve after the first
+                           deflate the last GMRES cycle of that first solve (its Krylov basis V
+                           and Arnoldi relation A V_k = V_{k+1} H, H = QR: U = V_k R^-1,
+                           C = V_{k+1} Q with A U = C; the initial residual is projected off C
+                           and every new Krylov vector orthogonalised against C); 0 = plain
+                           GMRES.  Not used with float pairs. */
 } sdbie_opts;
 
 typedef struct {
@@ -136,12 +142,12 @@ typedef struct sdbie_plan_s* sdbie_plan;
 
 /* Fill `o` with the defaults: tol_gmres 1e-10, tol_ddm 1e-8, theta 0.5,
  * maxit_gmres 500, restart 50, maxit_ddm 200, outer 1, slip 0, prec FP64,
- * tol_mixed 1e-4, refine_max 8, mixed_mode 2, relax_outer 1, local_solver 0. */
+ * tol_mixed 1e-4, refine_max 8, mixed_mode 2, relax_outer 1, local_solver 0, recycle 1. */
 void sdbie_default_opts(sdbie_opts* o);
 
 /* Bytes of device workspace a plan for n nodes (1 <= n <= 2^23) and GMRES
  * restart length up to max_restart (1..1000) needs (0 if the arguments are
- * invalid).  Roughly (64 max_restart + 1400) n bytes plus (n/256)^2 * 2. */
+ * invalid).  Roughly (88 max_restart + 1424) n bytes plus (n/256)^2 * 2. */
 size_t sdbie_workspace_bytes(int64_t n, int max_restart);
 
 /* Stage a surface: spatial (Morton) ordering, double and float copies of the

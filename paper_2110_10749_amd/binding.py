@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
                 ("maxit_gmres", ctypes.c_int), ("restart", ctypes.c_int), ("maxit_ddm", ctypes.c_int),
                 ("outer", ctypes.c_int), ("slip", ctypes.c_int), ("prec", ctypes.c_int),
                 ("tol_mixed", ctypes.c_double), ("refine_max", ctypes.c_int), ("mixed_mode", ctypes.c_int),
-                ("relax_outer", ctypes.c_int), ("local_solver", ctypes.c_int)]
+                ("relax_outer", ctypes.c_int), ("local_solver", ctypes.c_int), ("recycle", ctypes.c_int)]
 
 
 class KernelStat(ctypes.Structure):
@@ -65,7 +65,7 @@ class Info(ctypes.Structure):
 
 
 _lib = None
-ABI_VERSION = 3  # layout of the structs above (sdbie_abi_version)
+ABI_VERSION = 4  # layout of the structs above (sdbie_abi_version)
 
 
 def lib():

@@ -24,7 +24,7 @@ int64_t next_pow2(int64_t n) {
 
 struct Layout {
     size_t x, nrm, w, wn, px, pn, pw, px32, boxes, uboxes, mask64, mask32, perm, keys, partial, rec, red, scal, vecs,
-        basis_in, basis_out, image_out, total;
+        basis_in, basis_out, image_out, basis_rc, total;
 };
 
 Layout layout(int64_t n, int m) {
@@ -59,6 +59,7 @@ Layout layout(int64_t n, int m) {
     L.basis_in = take((size_t)(m + 1) * 3 * n * d);
     L.basis_out = take((size_t)(m + 1) * n * d);
     L.image_out = take((size_t)(m + 1) * 4 * n * d);
+    L.basis_rc = take((size_t)(m + 1) * 3 * n * d);
     L.total = off;
     return L;
 }
@@ -99,6 +100,7 @@ sdbie_opts checked_opts(const sdbie_opts* op, const Plan& P) {
     if (o.mixed_mode < 0 || o.mixed_mode > 2) fail(SDBIE_ERR_ARG, "mixed_mode must be 0, 1 or 2");
     if (o.relax_outer != 0 && o.relax_outer != 1) fail(SDBIE_ERR_ARG, "relax_outer must be 0 or 1");
     if (o.local_solver != 0 && o.local_solver != 1) fail(SDBIE_ERR_ARG, "local_solver must be 0 or 1");
+    if (o.recycle != 0 && o.recycle != 1) fail(SDBIE_ERR_ARG, "recycle must be 0 or 1");
     return o;
 }
 
@@ -157,6 +159,7 @@ void carve_workspace(Plan& P, void* ws) {
     P.basis_in = reinterpret_cast<double*>(b + L.basis_in);
     P.basis_out = reinterpret_cast<double*>(b + L.basis_out);
     P.image_out = reinterpret_cast<double*>(b + L.image_out);
+    P.basis_rc = reinterpret_cast<double*>(b + L.basis_rc);
 }
 
 }  // namespace sdbie
@@ -181,6 +184,7 @@ void sdbie_default_opts(sdbie_opts* o) {
     o->mixed_mode = 2;
     o->relax_outer = 1;
     o->local_solver = 0;
+    o->recycle = 1;
 }
 
 size_t sdbie_workspace_bytes(int64_t n, int max_restart) {
@@ -188,7 +192,7 @@ size_t sdbie_workspace_bytes(int64_t n, int max_restart) {
     return workspace_bytes(n, max_restart);
 }
 
-int sdbie_abi_version(void) { return 3; }
+int sdbie_abi_version(void) { return 4; }
 
 const char* sdbie_last_error(void) { return g_last_error.c_str(); }
 

@@ -129,6 +129,7 @@ struct Plan {
     double* basis_in = nullptr;   // inner GMRES basis [(max_restart+1)][3n]
     double* basis_out = nullptr;  // outer GMRES basis [(max_restart+1)][n]
     double* image_out = nullptr;  // local solutions (p, u) of each outer basis vector [(max_restart+1)][4n]
+    double* basis_rc = nullptr;   // recycled inner basis (deflation space) [(max_restart+1)][3n]
     double* host_pinned = nullptr;  // not used (host buffers are plain)
     // (target, source) pairs of real nodes in the near tile pairs (double, float masks)
     double near_pairs64 = 0.0, near_pairs32 = 0.0;

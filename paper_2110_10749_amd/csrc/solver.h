@@ -37,6 +37,7 @@ enum : int {
     kVecCoupledV,     // mixed coupled refinement: u.n / projected pressure
     kVecImage,        // interface solve: (p, u) combined from the image basis (4n: two slots)
     kVecImage2,
+    kVecRecycle,      // device coefficients of the deflation corrections
     kVecSpare,
 };
 static_assert(kVecSpare < kNumVec, "work-vector slots exceed the workspace");
@@ -66,6 +67,19 @@ struct GmresWS {
     double* x2 = nullptr;
 };
 
+// Deflation space carried from one local solve to later solves with the same
+// operator: the last GMRES cycle's basis V (k + 1 vectors of length ld) and
+// its Arnoldi relation A V_k = V_{k+1} H with H = Q R (the cycle's Givens
+// rotations and triangle), so that U = V_k R^-1 and C = V_{k+1} Q satisfy
+// A U = C with orthonormal C.  exact: the cycle used double products only.
+struct Recycle {
+    double* V = nullptr;
+    int64_t ld = 0;
+    int k = 0;
+    bool exact = true;
+    std::vector<double> cs, sn, R;  // R: k x k upper triangle, row-major
+};
+
 struct GmresOut {
     int iters = 0;
     int checks = 0;  // double-pair true residuals after cycles with float-pair products
@@ -90,6 +104,10 @@ struct Ctx {
     bool loose32 = false;
     // index of the Krylov basis vector the operator is being applied to (-1: a residual)
     int krylov_index = -1;
+    // deflation of the Stokes local solves (opts.recycle): rc_cur is set around
+    // a solve that may use (or, while empty, fill) the space
+    Recycle rc_stokes;
+    Recycle* rc_cur = nullptr;
 
     Ctx(Plan& plan, hipStream_t st, const sdbie_opts& opts);
     void finish();

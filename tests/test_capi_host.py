@@ -36,11 +36,11 @@ def test_exports_every_declared_symbol(L):
 
 def test_abi_version_and_default_opts(L):
     from paper_2110_10749_amd import binding
-    assert L.sdbie_abi_version() == 3
+    assert L.sdbie_abi_version() == 4
     o = binding.default_opts()
     assert o.tol_gmres == 1e-10 and o.tol_ddm == 1e-8 and o.theta == 0.5
     assert o.restart == 50 and o.outer == 1 and o.slip == 0 and o.prec == 0
-    assert o.tol_mixed == 1e-4 and o.mixed_mode == 2 and o.relax_outer == 1 and o.local_solver == 0
+    assert o.tol_mixed == 1e-4 and o.mixed_mode == 2 and o.relax_outer == 1 and o.local_solver == 0 and o.recycle == 1
 
 
 def test_workspace_bytes(L):

@@ -127,6 +127,25 @@ def test_table1_successive_approximations_match_oracle(sd, s16, golden):
     assert info["ddm_iters"] - 1 == ref["dn_sa_theta05"]
 
 
+def test_recycled_deflation_space(sd):
+    # FP64 ddm_solve with the Stokes solves deflated by the first one's last
+    # GMRES cycle: the same solution, fewer local iterations (perturbed sphere)
+    S = surfaces.perturbed_sphere(1.0 / 32, lmax=4, sigma=0.05, seed=0)
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / 32)
+    U = fields.unit_vector(11)
+    out = {}
+    for rc in (0, 1):
+        p, u, D, info = sd.ddm_solve(plan, 1.0, 1e-2, 1.0, U, None,
+                                     opts=dict(prec="fp64", recycle=rc, tol_gmres=1e-12, tol_ddm=1e-11))
+        print(rc, info, D, flush=True)
+        assert info["converged"]
+        out[rc] = (host(p), host(u), np.asarray(D), info["gmres_iters"])
+    assert rel(out[1][2], out[0][2]) < 1e-10
+    assert rel(out[1][1], out[0][1]) < 1e-8 and rel(out[1][0], out[0][0]) < 1e-8
+    assert out[1][3] < 0.9 * out[0][3]
+    plan.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_ddm_physical_mode_outer_gmres(sd, s16, prec):
     # the paper's interface conditions with slip (K = 1e-2, alpha = 1: beta = 10)
