@@ -889,8 +889,16 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
         dev_axpy_w(P, g, P.scal + kScalMean, -1.0 / P.area, s);
     };
     // y -> Abar_D^-T [base + Pi^T Nhat^T V^T S^-T (rhs3)],  rhs3 in tE
+    // the transposed Stokes solves share one operator: with double pairs the
+    // first fills the deflation space and the later ones use it (as in ddm_solve)
+    const bool rc_on = o.recycle && o.prec == SDBIE_FP64;
+    auto solve_ST = [&](const double* b, double* x) {
+        rc_cur = rc_on ? &rc_stokes : nullptr;
+        solve_T(opST, b, x, 3 * n);
+        rc_cur = nullptr;
+    };
     auto chain = [&](const double* base, double* out) {
-        solve_T(opST, tE, x2, 3 * n);   // x2 = S^-T rhs3
+        solve_ST(tE, x2);               // x2 = S^-T rhs3
         VT(x2, tG);                     // tG = V^T x2
         dev_normal_component(P, tG, tD, s);
         PiT(tD);
@@ -952,7 +960,7 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
     SLT(lam1, 1.0, tA);
     dev_scalar_normal(P, tA, mu / K, tE, s);
     dev_axpby(1.0, tE, 1.0, gu, tE, 3 * n, s);
-    solve_T(opST, tE, lam2, 3 * n);
+    solve_ST(tE, lam2);
 
     // position gradient
     double* v = P.vec(kVecRefR);
