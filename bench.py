@@ -13,7 +13,8 @@ final solves).  Every layer-sum pass evaluates N^2 (target, source) pairs;
 (inputs resident on the GPU).
 
 Also reported: the all-FP64 GPU path with the same settings and with strict
-interface products (every local solve to 1e-10), their drag, the drag of each
+interface products (every local solve to 1e-10), each the faster of with and
+without the recycled deflation space, their drag, the drag of each
 against the closed-form solution, the roofline of the dominant kernel (HIP-event
 durations recorded by the library around every pair-sum kernel during the timed
 region), and the CPU oracle's pair rate on a bounded sample of target rows of
@@ -240,17 +241,26 @@ def main() -> int:
     }
 
     if not args.no_fp64:
-        sd.ddm_solve(plan, mu, K, alpha, E, None, opts=opts_fp64)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        p64, u64, D64, info64 = sd.ddm_solve(plan, mu, K, alpha, E, None, opts=opts_fp64)
-        torch.cuda.synchronize()
-        t64 = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        _, _, D64s, info64s = sd.ddm_solve(plan, mu, K, alpha, E, None, opts=dict(opts_fp64, relax_outer=0))
-        torch.cuda.synchronize()
-        t64s = time.perf_counter() - t0
+        # the FP64 baselines at their best: with and without the recycled
+        # deflation space, the faster of the two (after a warm-up solve each)
+        def best_fp64(extra):
+            best = None
+            for rc in (1, 0):
+                o = dict(opts_fp64, recycle=rc, **extra)
+                sd.ddm_solve(plan, mu, K, alpha, E, None, opts=o)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = sd.ddm_solve(plan, mu, K, alpha, E, None, opts=o)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                if best is None or t < best[0]:
+                    best = (t, out, rc)
+            return best
+        t64, (p64, u64, D64, info64), rc64 = best_fp64({})
+        t64s, (_, _, D64s, info64s), rc64s = best_fp64({"relax_outer": 0})
         result.update({
+            "fp64_recycle": rc64,
+            "fp64_strict_recycle": rc64s,
             "fp64_strict_ms_per_solve": 1e3 * t64s,
             "speedup_mixed_vs_fp64_strict": t64s / (wall / args.steps),
             "drag_fp64_strict": flow(D64s),
