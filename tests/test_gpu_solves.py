@@ -262,3 +262,32 @@ def test_mixed_benchmark_mode_with_forcing(sd, s16):
     pb, ub, Db = O.coupled_dense_solve(geo, O.Params(1.0, 1e-2, 0.0), E, fx)
     assert info["converged"]
     assert rel(host(p), pb) < 1e-9 and rel(host(u), ub) < 1e-9 and rel(D, Db) < 1e-10
+
+
+def test_biem_accuracy_problems_converge_at_fifth_order(sd):
+    # section "BIEM accuracy" (its convergence figure): on a sphere of radius
+    # 0.8, the Darcy problem with the Neumann data of p = e^x sin y (K = mu =
+    # 1) and the Stokes problem of a point force (1,0,0) at (0.2,0,0) inside
+    # (traction data, no slip term), solved alone on the GPU; the errors fall
+    # like h^5 (ratios above 20 from h = 1/32 to 1/64; measured 32 and 37)
+    x0, gv = [0.2, 0.0, 0.0], [1.0, 0.0, 0.0]
+    ep, eu = [], []
+    for inv_h in (16, 32, 64):
+        S = surfaces.sphere(1.0 / inv_h, 0.8)
+        plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / inv_h)
+        pe, grad = exact.harmonic_exp_sin(S.x)
+        pe = pe - (S.w @ pe) / S.w.sum()
+        vn = -(grad * S.n).sum(axis=0)
+        p, info = sd.darcy_solve(plan, 1.0, 1.0, 0.0, dev(vn), opts=dict(prec="fp64", tol_gmres=1e-13))
+        assert info["converged"]
+        ep.append(float(np.sqrt(np.mean((host(p) - pe) ** 2))))
+        ue = exact.stokeslet_field(S.x, x0, gv)
+        f = exact.stokeslet_traction(S.x, S.n, x0, gv)
+        u, info = sd.stokes_solve(plan, 1.0, 1.0, 0.0, [0.0, 0.0, 0.0], torch.zeros(S.N, dtype=torch.float64, device="cuda"),
+                                  dev(f), opts=dict(prec="fp64", tol_gmres=1e-13))
+        assert info["converged"]
+        eu.append(float(np.sqrt(np.mean(((host(u) - ue) ** 2).sum(axis=0)))))
+        plan.close()
+    print("darcy", ep, "stokes", eu, flush=True)
+    assert ep[1] < 1e-5 and eu[1] < 1e-5
+    assert ep[1] / ep[2] > 20.0 and eu[1] / eu[2] > 20.0
