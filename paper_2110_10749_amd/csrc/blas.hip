@@ -162,7 +162,8 @@ __global__ void k_adj_darcy(int64_t n, const double* __restrict__ tn, const doub
     out[i] = tn[i] + lam[i] * dl1[i] + w[i] * sum[0] * inv_area;
 }
 
-// out = lam + sum_c mneg_c lam_c + tns + w n (*flux)/area + beta w P_tau sv
+// out = lam + sum_c mneg_c lam_c + tns + w n (*flux)/area + beta P_tau sv, where sv
+// already carries the target weight w
 // (transposed completed Stokes operator with slip); mneg_c[a][i] = -(M_i)_{ac}
 __global__ void k_adj_stokes(int64_t n, const double* __restrict__ lam, const double* __restrict__ m0,
                              const double* __restrict__ m1, const double* __restrict__ m2,
@@ -179,7 +180,7 @@ __global__ void k_adj_stokes(int64_t n, const double* __restrict__ lam, const do
     for (int a = 0; a < 3; ++a) {
         const int64_t k = a * n + i;
         double v = l[a] + m0[k] * l[0] + m1[k] * l[1] + m2[k] * l[2] + tns[k] + w[i] * nv[a] * fl;
-        if (sv) v += beta * w[i] * (sv[k] - svn * nv[a]);
+        if (sv) v += beta * (sv[k] - svn * nv[a]);  // sv carries the target weight
         out[k] = v;
     }
 }

@@ -505,6 +505,67 @@ struct StokesTNOp {
     }
 };
 
+// Transposed stresslet and transposed Stokeslet of one density (the adjoint's
+// transposed Stokes operator with slip), from one record and one rsqrt:
+//   out_i  = sum_j c_dl (q_j.D)(D.n_i) D s4/r^5
+//   out2_i = sum_j c_sl [q_j s1/r + D (D.q_j) s3/r^3]
+// (unit source weights), stored as six components [out | out2].
+template <typename T>
+struct StokesTNSLOp {
+    static constexpr int C = 6;
+    static constexpr int R = 8;
+    static constexpr int U = unroll_of<T, R>();
+    T xi, yi, zi, nxi, nyi, nzi;
+    double ax = 0.0, ay = 0.0, az = 0.0, bx = 0.0, by = 0.0, bz = 0.0, sl_scale = 0.0;
+    T tx = T(0), ty = T(0), tz = T(0), sx = T(0), sy = T(0), sz = T(0);
+    __device__ __forceinline__ static void pack(T* r, int64_t j, const KArgs& a) { StokesTNOp<T>::pack(r, j, a); }
+    __device__ __forceinline__ void init(const KArgs& a, int64_t i) {
+        xi = load_x<T>(a, 0, i);
+        yi = load_x<T>(a, 1, i);
+        zi = load_x<T>(a, 2, i);
+        nxi = T(a.nrm[i]);
+        nyi = T(a.nrm[a.npad + i]);
+        nzi = T(a.nrm[2 * a.npad + i]);
+        sl_scale = a.c_sl / a.c_dl;  // the record carries c_dl q
+    }
+    template <bool NEAR, class P>
+    __device__ __forceinline__ void pair(P r, T id, T id2, T rc2) {
+        const T dx = xi - r[0], dy = yi - r[1], dz = zi - r[2];
+        const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const T inv_r = rsq_pair<NEAR>(r2);
+        const T ir2 = inv_r * inv_r;
+        T k1 = inv_r, k2, k3 = inv_r * ir2, k4 = k3 * ir2;
+        if (NEAR && r2 < rc2) near_factors<T, true, false, true, true>(r2, inv_r, id, id2, k1, k2, k3, k4);
+        const T dq = fma(dx, r[3], fma(dy, r[4], dz * r[5]));
+        const T c = dq * fma(dx, nxi, fma(dy, nyi, dz * nzi)) * k4;
+        tx = fma(c, dx, tx);
+        ty = fma(c, dy, ty);
+        tz = fma(c, dz, tz);
+        const T cs = dq * k3;
+        sx = fma(r[3], k1, fma(cs, dx, sx));
+        sy = fma(r[4], k1, fma(cs, dy, sy));
+        sz = fma(r[5], k1, fma(cs, dz, sz));
+    }
+    __device__ __forceinline__ void flush() {
+        ax += (double)tx;
+        ay += (double)ty;
+        az += (double)tz;
+        bx += (double)sx;
+        by += (double)sy;
+        bz += (double)sz;
+        tx = ty = tz = sx = sy = sz = T(0);
+    }
+    __device__ __forceinline__ void store(const KArgs& a, int slot, int64_t i) const {
+        double* o = a.partial + (int64_t)slot * 6 * a.n;
+        o[i] = ax;
+        o[a.n + i] = ay;
+        o[2 * a.n + i] = az;
+        o[3 * a.n + i] = sl_scale * bx;
+        o[4 * a.n + i] = sl_scale * by;
+        o[5 * a.n + i] = sl_scale * bz;
+    }
+};
+
 // --------------------------------------------------------------------------
 // Position gradient of lam^T F (adjoint), double only.  See GradDesc.
 // G2/delta^5 = -(d/dr K2)/r and G4/delta^7 = -(d/dr K4)/r in the near field.
@@ -991,6 +1052,35 @@ void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
     const KArgs a = make_args(P, d, S, cut);
     const bool slip = d.sl && d.slip_beta != 0.0 && d.sl_dens == nullptr;
     const int code = (d.dl ? 1 : 0) | (d.sl ? 2 : 0) | (d.sub ? 4 : 0) | (slip ? 8 : 0);
+    if (d.target_normal && d.sl) {
+        // transposed stresslet and Stokeslet of one density: six outputs
+        // [out | out + 3n]; half the splits, so the partials fit the buffer
+        if (!d.dl || d.sub || d.sl_dens != d.dl_dens || !(d.c_dl != 0.0) || d.base || d.comp || d.add_const)
+            throw Error(SDBIE_ERR_ARG, "transposed Stokes pass: double and single layer of one density");
+        if (S < 2) {
+            PassDesc d1 = d, d2 = d;
+            d1.sl = false;
+            d2.dl = false;
+            d2.target_normal = false;
+            d2.out = d.out + 3 * P.n;
+            launch_stokes_pass(P, d1, st);
+            launch_stokes_pass(P, d2, st);
+            return;
+        }
+        const int S2 = S / 2;
+        const KArgs a2 = make_args(P, d, S2, cut);
+        if (d.mixed) launch_pair_kernels<StokesTNSLOp<float>, float>(P, a2, st, 1, 16 | 2 | 1, true);
+        else launch_pair_kernels<StokesTNSLOp<double>, double>(P, a2, st, 1, 16 | 2 | 1, false);
+        hipLaunchKernelGGL((epilogue<6>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P.n, 2 * S2,
+                           (const double*)P.partial, d.target_weight ? (const double*)P.w : nullptr, nullptr, 0.0,
+                           nullptr, 0.0, (const double*)P.nrm, 0.0, 0.0, 0.0, d.out,
+                           d.scatter ? (const int32_t*)P.perm : nullptr);
+        SDBIE_LAUNCHED();
+        Plan& Pm = const_cast<Plan&>(P);
+        (d.mixed ? Pm.applies_mixed : Pm.applies_fp64) += 1;
+        Pm.pairs += (double)P.n * (double)P.n;
+        return;
+    }
     if (d.target_normal) {
         if (!d.dl || d.sl || d.sub) throw Error(SDBIE_ERR_ARG, "transposed Stokes pass takes a double layer only");
         if (d.mixed) launch_pair_kernels<StokesTNOp<float>, float>(P, a, st, 1, 16 | 1, true);

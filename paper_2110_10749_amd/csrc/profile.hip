@@ -68,7 +68,11 @@ double flops_per_pair(int v) {
     decode(v, family, part, mixed, code);
     const bool dl = code & 1, sl = code & 2, sub = code & 4;
     if (family == 2 || part == 2) return 0.0;  // gradient: not counted
-    if (code & 16) return family == 0 ? 9.0 + 2 + 5 + 3 : 9.0 + 2 + 5 + 5 + 2 + 6;
+    if (code & 16) {
+        if (family == 0) return 9.0 + 2 + 5 + 3;
+        // transposed stresslet; with the Stokeslet of the same density: k3, D.q k3, acc += q k1 + c D
+        return 9.0 + 2 + 5 + 5 + 2 + 6 + (sl ? 1 + 1 + 12 : 0);
+    }
     // common: D (3), r^2 (1 mul + 2 fma = 5), rsqrt (1)
     double f = 9.0;
     if (family == 0) {

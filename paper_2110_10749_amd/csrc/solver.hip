@@ -767,7 +767,8 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
     double* tE = P.vec(kVecUl);      // 3n rhs of the transposed Stokes solve
     double* tA = P.vec(kVecDarcyB);  // transposed Darcy operator temp
     double* tB = P.vec(kVecStokesB); // transposed stresslet temp
-    double* tC = P.vec(kVecTraction);// transposed Stokeslet temp
+    double* tC = P.vec(kVecTraction);// transposed Stokeslet temp (follows tB)
+    static_assert(kVecTraction == kVecStokesB + 1, "the fused transposed pass writes tB and tC as one [6][n] block");
     double* x2 = P.vec(kVecIn);
     double* tG = P.vec(kVecOut);
     double* x1 = P.vec(kVecCoupledV);
@@ -828,17 +829,14 @@ void Ctx::adjoint(const sdbie_params& prm, const double U[3], const double* fx, 
         d.dl_dens = l;
         d.out = tB;
         d.mixed = m32;
-        launch_stokes_pass(P, d, s);
         if (beta != 0.0) {
-            PassDesc e2;
-            e2.sl = true;
-            e2.unit_src_weight = true;
-            e2.c_sl = 1.0 / (8.0 * kPi * mu);
-            e2.sl_dens = l;
-            e2.out = tC;
-            e2.mixed = m32;
-            launch_stokes_pass(P, e2, s);
+            // with slip, the transposed Stokeslet of the same density comes
+            // from the same pass, target-weighted, into tC = tB + 3n
+            d.sl = true;
+            d.c_sl = 1.0 / (8.0 * kPi * mu);
+            d.sl_dens = l;
         }
+        launch_stokes_pass(P, d, s);
         dev_normal_component(P, l, tD, s);
         dev_dot(P, tD, nullptr, n, P.scal + kScalCompS, s);
         dev_adj_stokes(P, l, m0, m1, m2, tB, beta != 0.0 ? tC : nullptr, P.scal + kScalCompS, beta, out, s);
