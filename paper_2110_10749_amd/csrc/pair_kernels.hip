@@ -370,6 +370,24 @@ struct StokesOp {
         const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const T inv_r = rsq_pair<NEAR>(r2);
         const T ir2 = inv_r * inv_r;
+        if constexpr (!NEAR && SL) {
+            // unsmoothed kernels: 1/r comes out of the sum,
+            //   acc += (1/r) [f + D (1/r^2) ((u.D)(D.n)/r^2 + D.f)]
+            // two multiplies fewer per pair than with k1, k3, k4 apart
+            const T fx = r[FX], fy = r[FY], fz = r[FZ];
+            T c = fma(dx, fx, fma(dy, fy, dz * fz));
+            if (DL) {
+                const T ux = r[UX] - uix, uy = r[UY] - uiy, uz = r[UZ] - uiz;
+                const T ud = fma(ux, dx, fma(uy, dy, uz * dz));
+                const T dn = fma(dx, r[NX], fma(dy, r[NY], dz * r[NZ]));
+                c = fma(ud * dn, ir2, c);
+            }
+            c *= ir2;
+            tx = fma(fma(c, dx, fx), inv_r, tx);
+            ty = fma(fma(c, dy, fy), inv_r, ty);
+            tz = fma(fma(c, dz, fz), inv_r, tz);
+            return;
+        }
         T k1 = inv_r, k2, k3 = inv_r * ir2, k4 = k3 * ir2;
         if (NEAR && r2 < rc2) near_factors<T, SL, false, SL, DL>(r2, inv_r, id, id2, k1, k2, k3, k4);
         T cd = T(0);

@@ -61,29 +61,36 @@ std::string prof_name(int v) {
     return s + ">";
 }
 
-// Algorithmic flops of one pair in its far-field form (the near kernel's
-// smoothing branch is not counted); 0 for the packing kernel.
+// Algorithmic flops of one pair in the far-field form the kernels evaluate
+// (an FMA counts two; the near kernel's smoothing branch is not counted); 0
+// for the packing kernel.
 double flops_per_pair(int v) {
     int family, part, mixed, code;
     decode(v, family, part, mixed, code);
     const bool dl = code & 1, sl = code & 2, sub = code & 4;
     if (family == 2 || part == 2) return 0.0;  // gradient: not counted
-    if (code & 16) {
-        if (family == 0) return 9.0 + 2 + 5 + 3;
-        // transposed stresslet; with the Stokeslet of the same density: k3, D.q k3, acc += q k1 + c D
-        return 9.0 + 2 + 5 + 5 + 2 + 6 + (sl ? 1 + 1 + 12 : 0);
-    }
     // common: D (3), r^2 (1 mul + 2 fma = 5), rsqrt (1)
-    double f = 9.0;
-    if (family == 0) {
-        if (dl) f += 2 + 5 + 4;       // k2 = inv_r^3 (2), D.n (5), (q_j - q_i) dn k2 + acc (4)
-        if (sl) f += 2;               // acc += g k1
-    } else {
-        f += 1 + (sl ? 1 : 0) + (dl ? 1 : 0);  // ir2, k3, k4
-        if (dl) f += (sub ? 3 : 0) + 5 + 5 + 2 + 6;  // u_j - u_i, (u.D), (D.n), c, acc += c D
-        if (sl) f += 5 + 1 + 12;                     // D.f, * k3, acc += f k1 + c D
+    const double common = 9.0;
+    if (code & 16) {
+        if (family == 0) return common + 2 + 5 + 3;  // k2 (2), D.n_i (5), acc += (q dn) k2 (3)
+        // transposed stresslet: ir2, k3, k4 (3), q.D (5), D.n_i (5), c (2), acc += c D (6);
+        // with the Stokeslet of the same density: cs = (q.D) k3 (1), acc2 += q k1 + cs D (12)
+        return common + 3 + 5 + 5 + 2 + 6 + (sl ? 1 + 12 : 0);
     }
-    return f;
+    if (family == 0) {
+        double f = common;
+        if (dl) f += 2 + 5 + (sub ? 4 : 3);  // k2 = inv_r^3 (2), D.n (5), (q_j - q_i) dn k2 + acc
+        if (sl) f += 2;                      // acc += g k1
+        return f;
+    }
+    if (sl) {
+        // acc += (1/r) [f + D ir2 ((u.D)(D.n) ir2 + D.f)]: ir2 (1), D.f (5), c *= ir2 (1),
+        // per component fma(c, d, f) and fma(., 1/r, acc) (12); the double layer adds
+        // u_j - u_i (3), u.D (5), D.n (5), (u.D)(D.n) (1) and its fma into c (2)
+        return common + 1 + 5 + 1 + 12 + (dl ? (sub ? 3 : 0) + 5 + 5 + 1 + 2 : 0);
+    }
+    // double layer alone: ir2, k3, k4 (3), u_j - u_i, u.D, D.n, c = (u.D)(D.n) k4 (2), acc += c D
+    return common + 3 + (sub ? 3 : 0) + 5 + 5 + 2 + 6;
 }
 
 ProfScope::ProfScope(int variant, double pairs, hipStream_t s) : s_(s) {
