@@ -37,6 +37,10 @@ constexpr int kRecBytes = 128;   // largest per-source record of a pair pass
 #ifndef SDBIE_GROUP_BYTES_F32
 #define SDBIE_GROUP_BYTES_F32 128
 #endif
+// far- and near-field blocks of a pass in one launch (1) or in two (0)
+#ifndef SDBIE_ONE_LAUNCH
+#define SDBIE_ONE_LAUNCH 1
+#endif
 // float far-field records through LDS (1) or the scalar cache (0)
 #ifndef SDBIE_FAR_LDS
 #define SDBIE_FAR_LDS 1

@@ -762,10 +762,10 @@ __device__ __forceinline__ void pair_group(Op& op, src_ptr<T> r, T id, T id2, T 
 // its split's range whose pairs are all beyond the cutoff (mask 0).  No
 // smoothing code is compiled in: every pair uses the plain 1/r^p kernels.
 template <class Op, typename T>
-__global__ __launch_bounds__(kTPB) void far_pairs(KArgs a) {
+__device__ __forceinline__ void far_body(const KArgs& a, int blk) {
     static_assert(kTile % Op::U == 0, "unroll must divide the tile");
-    const int split = blockIdx.x % a.nsplit;
-    const int b = blockIdx.x / a.nsplit;
+    const int split = blk % a.nsplit;
+    const int b = blk / a.nsplit;
     const int64_t i = (int64_t)b * kTPB + threadIdx.x;  // < npad
     Op op;
     op.init(a, i);
@@ -785,6 +785,11 @@ __global__ __launch_bounds__(kTPB) void far_pairs(KArgs a) {
     if (i < a.n) op.store(a, split, i);
 }
 
+template <class Op, typename T>
+__global__ __launch_bounds__(kTPB) void far_pairs(KArgs a) {
+    far_body<Op, T>(a, blockIdx.x);
+}
+
 // Far-field pass in float: the block stages each source tile in LDS (one
 // record per thread, coalesced; the next tile is loaded into registers while
 // the current one is summed) and every wave reads the records back as
@@ -793,7 +798,7 @@ __global__ __launch_bounds__(kTPB) void far_pairs(KArgs a) {
 // form beats scalar-cache records once half the pair's instructions would
 // read one.
 template <class Op>
-__global__ __launch_bounds__(kTPB) void far_pairs_lds(KArgs a) {
+__device__ __forceinline__ void far_lds_body(const KArgs& a, int blk) {
     using T = float;
     typedef float f4 __attribute__((ext_vector_type(4)));
     constexpr int R = Op::R, Q = R / 4;
@@ -801,8 +806,8 @@ __global__ __launch_bounds__(kTPB) void far_pairs_lds(KArgs a) {
     static_assert(kTile == kTPB, "one record per thread when staging a tile");
     static_assert(kTile % Op::U == 0, "unroll must divide the tile");
     __shared__ f4 tile[kTile * Q];
-    const int split = blockIdx.x % a.nsplit;
-    const int b = blockIdx.x / a.nsplit;
+    const int split = blk % a.nsplit;
+    const int b = blk / a.nsplit;
     const int64_t i = (int64_t)b * kTPB + threadIdx.x;  // < npad
     Op op;
     op.init(a, i);
@@ -850,21 +855,26 @@ __global__ __launch_bounds__(kTPB) void far_pairs_lds(KArgs a) {
     if (i < a.n) op.store(a, split, i);
 }
 
+template <class Op>
+__global__ __launch_bounds__(kTPB) void far_pairs_lds(KArgs a) {
+    far_lds_body<Op>(a, blockIdx.x);
+}
+
 // Near-field pass: the tiles of the target tile's mask row, cut into units of
 // kNearUnit sources dealt round-robin to the splits.  A (wave, unit) pair
 // whose boxes are at least the cutoff apart (and which holds no padding node)
 // runs the plain far-field body; every other pair takes the smoothing branch
 // when r < rho_cut delta.
 template <class Op, typename T>
-__global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
+__device__ __forceinline__ void near_body(const KArgs& a, int blk) {
     // the double smoothing branch is long: one record per step keeps its registers in bounds
     constexpr int NU = sizeof(T) == 8 ? 1 : Op::U;
     // far units: half the far kernel's unroll (the near kernel holds more scalars)
     constexpr int FU = Op::U > 1 ? Op::U / 2 : 1;
     static_assert(kNearUnit % NU == 0 && kNearUnit % FU == 0, "unroll must divide the near unit");
     static_assert(kNearUnit == 64, "one wave of targets per unit test");
-    const int split = blockIdx.x % a.nsplit;
-    const int b = blockIdx.x / a.nsplit;
+    const int split = blk % a.nsplit;
+    const int b = blk / a.nsplit;
     const int64_t i = (int64_t)b * kTPB + threadIdx.x;
     Op op;
     op.init(a, i);
@@ -922,6 +932,33 @@ __global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
         }
     }
     if (i < a.n) op.store(a, a.nsplit + split, i);
+}
+
+template <class Op, typename T>
+__global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
+    near_body<Op, T>(a, blockIdx.x);
+}
+
+// Far and near blocks of one pass in a single launch: blocks [0, T S) run the
+// far-field body, blocks [T S, 2 T S) the near-field one.  The far blocks are
+// dispatched first and the near blocks fill the CUs as the far ones drain, so
+// the pass does not wait for the far launch's last wave before the near work
+// starts.  Both write disjoint partial slots.  The register count of the
+// launch is that of the larger body: the same for the float passes; for the
+// double Stokes ones the near body's (76 against 46 VGPRs, 6 waves per SIMD
+// instead of 8), which costs the far blocks less than the drain it removes.
+template <class Op>
+__global__ __launch_bounds__(kTPB) void pass_pairs_lds(KArgs a) {
+    const int nfar = a.ntiles * a.nsplit;
+    if ((int)blockIdx.x < nfar) far_lds_body<Op>(a, blockIdx.x);
+    else near_body<Op, float>(a, (int)blockIdx.x - nfar);
+}
+
+template <class Op, typename T>
+__global__ __launch_bounds__(kTPB) void pass_pairs(KArgs a) {
+    const int nfar = a.ntiles * a.nsplit;
+    if ((int)blockIdx.x < nfar) far_body<Op, T>(a, blockIdx.x);
+    else near_body<Op, T>(a, (int)blockIdx.x - nfar);
 }
 
 // Sum the 2 nsplit partial slots of each target in a fixed order, then
@@ -992,6 +1029,16 @@ void launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int fami
         SDBIE_LAUNCHED();
     }
     const dim3 grid((unsigned)((int64_t)a.ntiles * a.nsplit));
+    if constexpr (SDBIE_ONE_LAUNCH) {
+        // far and near blocks in one launch (timed as one kernel, all N^2 pairs)
+        ProfScope prof(prof_variant(family, mixed, code, 3), all, st);
+        if constexpr (sizeof(T) == 4 && SDBIE_FAR_LDS)
+            hipLaunchKernelGGL((pass_pairs_lds<Op>), dim3(2 * grid.x), dim3(kTPB), 0, st, a);
+        else
+            hipLaunchKernelGGL((pass_pairs<Op, T>), dim3(2 * grid.x), dim3(kTPB), 0, st, a);
+        SDBIE_LAUNCHED();
+        return;
+    }
     {
         ProfScope prof(prof_variant(family, mixed, code, 0), all - near, st);
         if constexpr (sizeof(T) == 4 && SDBIE_FAR_LDS)

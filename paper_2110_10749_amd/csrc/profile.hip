@@ -30,7 +30,8 @@ std::vector<Rec> g_recs;
 
 // variant = ((family * 4 + part) * 2 + mixed) * 32 + code
 // family: 0 Laplace, 1 Stokes, 2 position gradient; part: 0 far kernel,
-// 1 near kernel, 2 source-record packing; code: DL 1, SL 2, SUB 4, SLIP 8,
+// 1 near kernel, 2 source-record packing, 3 far and near blocks in one
+// launch; code: DL 1, SL 2, SUB 4, SLIP 8,
 // transposed (target normal) 16.
 int prof_variant(int family, bool mixed, int code, int part) {
     return ((family * 4 + part) * 2 + (mixed ? 1 : 0)) * 32 + code;
@@ -48,7 +49,7 @@ void decode(int v, int& family, int& part, int& mixed, int& code) {
 std::string prof_name(int v) {
     int family, part, mixed, code;
     decode(v, family, part, mixed, code);
-    static const char* parts[] = {"far", "near", "pack", "?"};
+    static const char* parts[] = {"far", "near", "pack", "pass"};
     std::string s = family == 0 ? "laplace" : family == 1 ? "stokes" : "position_gradient";
     if (code & 16) s += "_T";
     s += std::string("_") + parts[part] + "<" + (mixed ? "f32" : "f64");
