@@ -954,8 +954,20 @@ __global__ __launch_bounds__(kTPB) void pass_pairs_lds(KArgs a) {
     else near_body<Op, float>(a, (int)blockIdx.x - nfar);
 }
 
+// Scalar-cache records (the double passes).  The double near body alone
+// would take 76 VGPRs (6 waves per SIMD); held to 8 waves per SIMD the
+// compiler keeps 64 and spills a few words outside the pair loops, and the
+// double passes run 3-4% faster.  The position-gradient passes hold far more
+// state and keep their registers.
 template <class Op, typename T>
-__global__ __launch_bounds__(kTPB) void pass_pairs(KArgs a) {
+__global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(8))) void pass_pairs(KArgs a) {
+    const int nfar = a.ntiles * a.nsplit;
+    if ((int)blockIdx.x < nfar) far_body<Op, T>(a, blockIdx.x);
+    else near_body<Op, T>(a, (int)blockIdx.x - nfar);
+}
+
+template <class Op, typename T>
+__global__ __launch_bounds__(kTPB) void pass_pairs_wide(KArgs a) {
     const int nfar = a.ntiles * a.nsplit;
     if ((int)blockIdx.x < nfar) far_body<Op, T>(a, blockIdx.x);
     else near_body<Op, T>(a, (int)blockIdx.x - nfar);
@@ -1016,8 +1028,14 @@ KArgs make_args(const Plan& P, const PassDesc& d, int nsplit, double cut) {
     return a;
 }
 
-// pack, far and near kernels of one pass, each timed on its own when
-// kernel timing is on (pairs: real-node pairs of the far / near tile pairs)
+template <class Op>
+struct family_is_gradient { static constexpr bool value = false; };
+template <bool SWAP>
+struct family_is_gradient<GradOp<SWAP>> { static constexpr bool value = true; };
+
+// pack and pair kernels of one pass, each timed on its own when kernel timing
+// is on (pairs: all N^2 for a pass kernel; with separate far and near
+// launches, the real-node pairs of the far / near tile pairs)
 template <class Op, typename T>
 void launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int family, int code, bool mixed) {
     static_assert(Op::R * sizeof(T) <= kRecBytes, "record larger than its workspace slot");
@@ -1034,6 +1052,8 @@ void launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int fami
         ProfScope prof(prof_variant(family, mixed, code, 3), all, st);
         if constexpr (sizeof(T) == 4 && SDBIE_FAR_LDS)
             hipLaunchKernelGGL((pass_pairs_lds<Op>), dim3(2 * grid.x), dim3(kTPB), 0, st, a);
+        else if constexpr (family_is_gradient<Op>::value)
+            hipLaunchKernelGGL((pass_pairs_wide<Op, T>), dim3(2 * grid.x), dim3(kTPB), 0, st, a);
         else
             hipLaunchKernelGGL((pass_pairs<Op, T>), dim3(2 * grid.x), dim3(kTPB), 0, st, a);
         SDBIE_LAUNCHED();
