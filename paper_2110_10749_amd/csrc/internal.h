@@ -50,7 +50,7 @@ constexpr int kRecBytes = 128;   // largest per-source record of a pair pass
 #endif
 constexpr int kMaxRestart = 1000; // largest GMRES restart length of a plan
 #ifndef SDBIE_SPLIT_TARGET
-#define SDBIE_SPLIT_TARGET 8192      // pair-kernel grids aim for at least this many blocks (fills the 8 waves per SIMD about 4 times at the benchmark size)
+#define SDBIE_SPLIT_TARGET 4096      // far-field blocks a pass kernel aims for (the near-field blocks double them)
 #endif
 // accepted input range: |coordinates| <= kMaxCoord, delta in [kMinDelta, kMaxCoord],
 // so every pair distance squared is a normal number in float and double
