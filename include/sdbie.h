@@ -147,7 +147,7 @@ void sdbie_default_opts(sdbie_opts* o);
 
 /* Bytes of device workspace a plan for n nodes (1 <= n <= 2^23) and GMRES
  * restart length up to max_restart (1..1000) needs (0 if the arguments are
- * invalid).  Roughly (88 max_restart + 1105 + 48 S) n bytes plus
+ * invalid).  Roughly (88 max_restart + 1105 + 96 S) n bytes plus
  * (n/256)^2 * 2, with S the source splits of a pair pass (a multiple of 8
  * up to 64: 64 at n = 4096, 16 at n = 68166, 8 from n = 131072 on). */
 size_t sdbie_workspace_bytes(int64_t n, int max_restart);

@@ -51,7 +51,7 @@ Layout layout(int64_t n, int m) {
     L.mask32 = take(nt * nt);
     L.perm = take(n * sizeof(int32_t));
     L.keys = take(next_pow2(n) * sizeof(uint64_t));
-    L.partial = take((size_t)2 * choose_splits(n) * 3 * n * d);
+    L.partial = take((size_t)2 * choose_splits(n) * 6 * n * d);  // up to six components per pass
     L.rec = take((size_t)npad * kRecBytes);
     L.red = take((size_t)kRedBlocks * (m + 2) * d);
     L.scal = take((size_t)(kScalGmres + 6 * (m + 2) + 64 > 1024 ? kScalGmres + 6 * (m + 2) + 64 : 1024) * d);

@@ -125,7 +125,7 @@ struct Plan {
     uint64_t* keys = nullptr; // sort scratch, [npow2]
     int64_t npow2 = 0;
     // scratch
-    double* partial = nullptr;  // [2 * nsplit][3][n]: far splits then near splits
+    double* partial = nullptr;  // [2 * nsplit][C][n], C <= 6: far splits then near splits
     void* rec = nullptr;        // per-pass source records, [npad][kRecBytes]
     double* red = nullptr;      // reduction partials [kRedBlocks * 64]
     double* scal = nullptr;     // small device scalars / columns [256]

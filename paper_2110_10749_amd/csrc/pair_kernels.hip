@@ -1139,24 +1139,12 @@ void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
     const int code = (d.dl ? 1 : 0) | (d.sl ? 2 : 0) | (d.sub ? 4 : 0) | (slip ? 8 : 0);
     if (d.target_normal && d.sl) {
         // transposed stresslet and Stokeslet of one density: six outputs
-        // [out | out + 3n]; half the splits, so the partials fit the buffer
+        // [out | out + 3n] (the partial buffer holds six components per slot)
         if (!d.dl || d.sub || d.sl_dens != d.dl_dens || !(d.c_dl != 0.0) || d.base || d.comp || d.add_const)
             throw Error(SDBIE_ERR_ARG, "transposed Stokes pass: double and single layer of one density");
-        if (S < 2) {
-            PassDesc d1 = d, d2 = d;
-            d1.sl = false;
-            d2.dl = false;
-            d2.target_normal = false;
-            d2.out = d.out + 3 * P.n;
-            launch_stokes_pass(P, d1, st);
-            launch_stokes_pass(P, d2, st);
-            return;
-        }
-        const int S2 = S / 2;
-        const KArgs a2 = make_args(P, d, S2, cut);
-        if (d.mixed) launch_pair_kernels<StokesTNSLOp<float>, float>(P, a2, st, 1, 16 | 2 | 1, true);
-        else launch_pair_kernels<StokesTNSLOp<double>, double>(P, a2, st, 1, 16 | 2 | 1, false);
-        hipLaunchKernelGGL((epilogue<6>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P.n, 2 * S2,
+        if (d.mixed) launch_pair_kernels<StokesTNSLOp<float>, float>(P, a, st, 1, 16 | 2 | 1, true);
+        else launch_pair_kernels<StokesTNSLOp<double>, double>(P, a, st, 1, 16 | 2 | 1, false);
+        hipLaunchKernelGGL((epilogue<6>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P.n, 2 * S,
                            (const double*)P.partial, d.target_weight ? (const double*)P.w : nullptr, nullptr, 0.0,
                            nullptr, 0.0, (const double*)P.nrm, 0.0, 0.0, 0.0, d.out,
                            d.scatter ? (const int32_t*)P.perm : nullptr);
