@@ -39,7 +39,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Published vector peaks.  FP32: 256 CU x 128 lanes x 2 flop x 2.4 GHz = 157.3
-# TFLOP/s, reached without packed instructions (this build disables them):
+# TFLOP/s, reached without packed instructions (the library is compiled without them):
 # an FP32 VALU instruction whose operands are all VGPRs issues every 2 cycles
 # per wave64 (probe: 2.05-2.5), one that reads an SGPR every 4 cycles.
 # FP64: 78.6 TFLOP/s (probe: 4.3 cycles per wave64 FMA).
@@ -132,7 +132,7 @@ def main() -> int:
                          "byte counters of a profiler) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               f"(the multi-GPU sharding is a design only).", file=sys.stderr)
         return 2
 
