@@ -54,6 +54,15 @@ def test_workspace_bytes(L):
     assert binding.workspace_bytes(100, 1000) > 0 and binding.workspace_bytes(100, 1001) == 0
 
 
+@pytest.mark.parametrize("n,m,splits", [(4096, 50, 64), (68166, 50, 16), (68166, 1000, 16), (351866, 50, 8)])
+def test_workspace_formula_in_header(L, n, m, splits):
+    # the header's estimate (88 m + 1105 + 96 S) n + (n/256)^2 * 2, within 1%
+    from paper_2110_10749_amd import binding
+    nt = (n + 255) // 256
+    est = (88 * m + 1105 + 96 * splits) * n + 2 * nt * nt
+    assert abs(est / binding.workspace_bytes(n, m) - 1.0) < 0.01
+
+
 def test_invalid_arguments_are_rejected_on_the_host(L):
     from paper_2110_10749_amd import binding as B
     # null plan pointer / null surface
