@@ -133,8 +133,10 @@ struct Ctx {
 
     void darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonzero, const double* extra_rhs,
                bool remove_mean = true);
+    // p_zero: p is known to be zero (then, without fx or lagged slip, the
+    // right-hand side is U itself and its single-layer pass is skipped)
     void stokes(const sdbie_params& prm, const double U[3], const double* p, const double* fx, double* u,
-                bool u_nonzero, const double* extra_rhs);
+                bool u_nonzero, const double* extra_rhs, bool p_zero = false);
     void ddm(const sdbie_params& prm, const double U[3], const double* fx, double* p, double* u, double drag[3]);
     void ddm_outer(const sdbie_params& prm, const double U[3], const double* fx, const double* r1, const double* r2,
                    double* p, double* u, bool remove_mean, double tol);

@@ -423,15 +423,20 @@ void Ctx::darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonz
 }
 
 void Ctx::stokes(const sdbie_params& prm, const double U[3], const double* p, const double* fx, double* u,
-                 bool u_nonzero, const double* extra_rhs) {
+                 bool u_nonzero, const double* extra_rhs, bool p_zero) {
     const int64_t n = P.n;
     const double beta = prm.alpha * prm.mu / std::sqrt(prm.K);
     double* f = P.vec(kVecTraction);
     double* rhs = P.vec(kVecStokesB);
     const bool lagged = o.slip == 1 && beta != 0.0;
-    // traction without the implicit slip term (lagged slip uses the entry u)
-    dev_traction(P, p, lagged ? u : nullptr, lagged ? beta : 0.0, fx, f, s);
-    single_layer_stokes(f, prm.mu, -1.0, U, rhs, (corr && debug_level() < 10) || loose32);
+    if (p_zero && !fx && !lagged) {
+        // zero traction: V[f] = 0, so the right-hand side is the uniform U
+        for (int c = 0; c < 3; ++c) dev_fill(U[c], rhs + c * n, n, s);
+    } else {
+        // traction without the implicit slip term (lagged slip uses the entry u)
+        dev_traction(P, p, lagged ? u : nullptr, lagged ? beta : 0.0, fx, f, s);
+        single_layer_stokes(f, prm.mu, -1.0, U, rhs, (corr && debug_level() < 10) || loose32);
+    }
     if (extra_rhs) dev_axpby(1.0, rhs, 1.0, extra_rhs, rhs, 3 * n, s);
     const double b_impl = lagged ? 0.0 : beta;
     // every Stokes solve of one call has the same operator: the first fills the
@@ -460,7 +465,7 @@ void Ctx::ddm(const sdbie_params& prm, const double U[3], const double* fx, doub
         bool first = true;
         for (int k = 1; k <= o.maxit_ddm; ++k) {
             darcy(prm, v, p, !first, nullptr);
-            stokes(prm, U, p, fx, u, !first, nullptr);
+            stokes(prm, U, p, fx, u, !first, nullptr, first);  // first: v = 0, hence p = 0
             first = false;
             dev_normal_component(P, u, vn, s);
             dev_axpby(1.0 - o.theta, v, o.theta, vn, vn, n, s);
@@ -532,7 +537,7 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
         project_mean(pl, pp);
         pstk = pp;
     }
-    stokes(prm, U, pstk, fx, ul, false, r2);
+    stokes(prm, U, pstk, fx, ul, false, r2, r1 == nullptr);  // T(0): p = 0 without a Darcy source
     dev_normal_component(P, ul, t0, s);
     const double t0n = relax ? norm(t0, n) : 0.0;
     if (image) {
