@@ -180,7 +180,7 @@ LONG = os.environ.get("SDBIE_LONG_TESTS") == "1"
 
 
 @pytest.mark.parametrize("inv_h", [32, pytest.param(64, marks=pytest.mark.skipif(
-    not LONG, reason="42 tight FP64 solves at N = 71002 take about 6.5 minutes; set SDBIE_LONG_TESTS=1"))])
+    not LONG, reason="42 tight FP64 solves at N = 71002 take about 5 minutes; set SDBIE_LONG_TESTS=1"))])
 def test_adjoint_perturbed_central_differences(sd, inv_h):
     S = make_surface("perturbed", 1.0 / inv_h)
     delta = 3.0 / inv_h
