@@ -943,10 +943,9 @@ __global__ __launch_bounds__(kTPB) void near_pairs(KArgs a) {
 // far-field body, blocks [T S, 2 T S) the near-field one.  The far blocks are
 // dispatched first and the near blocks fill the CUs as the far ones drain, so
 // the pass does not wait for the far launch's last wave before the near work
-// starts.  Both write disjoint partial slots.  The register count of the
-// launch is that of the larger body: the same for the float passes; for the
-// double Stokes ones the near body's (76 against 46 VGPRs, 6 waves per SIMD
-// instead of 8), which costs the far blocks less than the drain it removes.
+// starts.  Both write disjoint partial slots.  The register count of a
+// launch is that of its larger body: the same for the float passes; the
+// double passes are held to 8 waves per SIMD (pass_pairs below).
 template <class Op>
 __global__ __launch_bounds__(kTPB) void pass_pairs_lds(KArgs a) {
     const int nfar = a.ntiles * a.nsplit;
@@ -966,6 +965,7 @@ __global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(8))) void 
     else near_body<Op, T>(a, (int)blockIdx.x - nfar);
 }
 
+// The same without the wave target (position-gradient passes).
 template <class Op, typename T>
 __global__ __launch_bounds__(kTPB) void pass_pairs_wide(KArgs a) {
     const int nfar = a.ntiles * a.nsplit;
