@@ -131,8 +131,10 @@ struct Ctx {
     void solve(const std::function<void(const double*, double*, bool)>& op, const double* b, double* x, int64_t L,
                bool x_nonzero, double* rbuf, double* cbuf);
 
+    // v_zero: v is known to be zero (then, without an extra right-hand side,
+    // b = 0 and its single-layer pass is skipped)
     void darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonzero, const double* extra_rhs,
-               bool remove_mean = true);
+               bool remove_mean = true, bool v_zero = false);
     // p_zero: p is known to be zero (then, without fx or lagged slip, the
     // right-hand side is U itself and its single-layer pass is skipped)
     void stokes(const sdbie_params& prm, const double U[3], const double* p, const double* fx, double* u,

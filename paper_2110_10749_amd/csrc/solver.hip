@@ -408,11 +408,12 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op3, co
 // local problems
 // ------------------------------------------------------------------------------
 void Ctx::darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonzero, const double* extra_rhs,
-                bool remove_mean) {
+                bool remove_mean, bool v_zero) {
     const int64_t n = P.n;
     double* b = P.vec(kVecDarcyB);
     // b = -S_L[g], g = dp/dn = -(mu/K) v   =>  b = (mu/K) S_L[v]
-    single_layer_laplace(v, prm.mu / prm.K, b, (corr && debug_level() < 10) || loose32);
+    if (v_zero) dev_fill(0.0, b, n, s);
+    else single_layer_laplace(v, prm.mu / prm.K, b, (corr && debug_level() < 10) || loose32);
     if (extra_rhs) dev_axpby(1.0, b, 1.0, extra_rhs, b, n, s);
     solve([&](const double* in, double* out, bool mx) { op_darcy(in, out, mx); }, b, p, n, p_nonzero,
           P.vec(kVecRefR), P.vec(kVecRefC));
@@ -464,7 +465,7 @@ void Ctx::ddm(const sdbie_params& prm, const double U[3], const double* fx, doub
         dev_fill(0.0, u, 3 * n, s);
         bool first = true;
         for (int k = 1; k <= o.maxit_ddm; ++k) {
-            darcy(prm, v, p, !first, nullptr);
+            darcy(prm, v, p, !first, nullptr, true, first);           // first: v = 0
             stokes(prm, U, p, fx, u, !first, nullptr, first);  // first: v = 0, hence p = 0
             first = false;
             dev_normal_component(P, u, vn, s);
@@ -528,7 +529,7 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
     // t0 = T(0)
     if (r1) {
         dev_fill(0.0, v, n, s);
-        darcy(prm, v, pl, false, r1, remove_mean);
+        darcy(prm, v, pl, false, r1, remove_mean, true);  // v = 0: b = r1
     } else {
         dev_fill(0.0, pl, n, s);
     }
