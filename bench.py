@@ -13,12 +13,15 @@ final solves).  Every layer-sum pass evaluates N^2 (target, source) pairs;
 (inputs resident on the GPU).
 
 Also reported: the all-FP64 GPU path with the same settings and with strict
-interface products (every local solve to 1e-10), each the faster of with and
-without the recycled deflation space, their drag, the drag of each
-against the closed-form solution, the roofline of the dominant kernel (HIP-event
-durations recorded by the library around every pair-sum kernel during the timed
-region), and the CPU oracle's pair rate on a bounded sample of target rows of
-the same surface.
+interface products (every local solve to 1e-10), each the median of 3 solves
+and the faster of with and without the recycled deflation space, their drag,
+the drag of each against the closed-form solution, the staging time of the
+surface (once per surface, outside the solve), the roofline of the dominant
+kernel (HIP-event durations recorded by the library around every pair-sum
+kernel during the timed region), and the CPU oracle on a bounded sample of
+target rows of the same surface: its pair rate, and the residual of the mixed
+solve's (p, u) in both coupled equations that its pair sums give (the error
+of the GPU solution against the FP64 oracle).
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload sphere-h64|perturbed-h128]
 
@@ -52,43 +55,66 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(S, delta, budget_s: float = 15.0):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(S, delta, prm, U, p, u, budget_s: float = 15.0):
     """Oracle (plain FP64 C loops, OpenMP over targets) on sampled target rows.
 
-    The sample is every layer kind the solve uses (Laplace single and
-    subtracted double layer, Stokes single and subtracted double layer)
-    evaluated on M targets against all N sources; M is sized for ~budget_s
-    of CPU time.  Pairs/s = 4 M N / time.
+    The sample is the residual of the GPU's solution (p, u) in both coupled
+    equations, evaluated by the oracle: the Laplace subtracted double layer
+    of p and single layer of u.n, the Stokes subtracted double layer of u and
+    single layers of -p n and of the slip traction, each on M target rows
+    against all N sources; M is sized for ~budget_s of CPU time.
+    Pairs/s = 5 M N / time (4 without slip).
+    The same evaluation is the stated error of the GPU solve against the
+    FP64 oracle: the relative root-mean-square residuals on the M rows
+    (Darcy rows up to the constant that the completion fixes).
     """
     import numpy as np
 
     from oracle import oracle as O
-    from workloads import fields
 
     geo = O.Geometry(S.x, S.n, S.w, delta)
-    q = fields.random_scalar(S.N, 1)
-    u = fields.random_vector(S.N, 2)
+    oprm = O.Params(*prm)
 
     def run(M):
-        t = np.linspace(0, S.N - 1, M).astype(np.int64)
+        t = np.unique(np.linspace(0, S.N - 1, M).astype(np.int64))
         t0 = time.perf_counter()
-        O.laplace_apply(geo, O.LSL, q, t)
-        O.laplace_apply(geo, O.LDLS, q, t)
-        O.stokes_apply(geo, 1.0, O.SSL, u, t)
-        O.stokes_apply(geo, 1.0, O.SDLS, u, t)
-        return time.perf_counter() - t0
+        res = O.coupled_residual(geo, oprm, U, p, u, t)
+        return time.perf_counter() - t0, t, res
 
     # size the sample from probes until it takes at least half the budget
-    M, dt = 64, run(64)
+    M = 64
+    dt, t, res = run(M)
     for _ in range(4):
         if dt >= 0.5 * budget_s or M >= S.N:
             break
         M = int(max(M + 1, min(S.N, M * budget_s / max(dt, 1e-6))))
-        dt = run(M)
-    return {"value": 4.0 * M * S.N / dt, "unit": "pair-interactions/s", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"4 layer applies (Laplace SL, Laplace DL-subtracted, Stokes SL, Stokes DL-subtracted) "
-                      f"on {M} of {S.N} target rows x all {S.N} sources, FP64, {dt:.1f} s"}
+        dt, t, res = run(M)
+    r1, b1, r2, b2 = res
+    rms = lambda a: float(np.sqrt(np.mean(np.asarray(a) ** 2)))
+    resid = {"darcy": rms(r1 - r1.mean()) / rms(b1), "stokes": rms(r2) / rms(b2),
+             "rows": int(len(t)),
+             "definition": "RMS over the sampled rows of A_D p - (mu/K) S_L[u.n] (minus its mean) relative to that "
+                           "of (mu/K) S_L[u.n], and of A_S u + (w.n.u/|S|) n + V[beta P_tau u] - (U - V[-p n]) "
+                           "relative to that of U - V[-p n]; FP64 oracle pair loops"}
+    napply = 5 if oprm.beta != 0.0 else 4
+    base = {"value": napply * len(t) * S.N / dt, "unit": "pair-interactions/s", "cores": O.num_threads(),
+            "cpu_model": cpu_model(), "kind": "oracle",
+            "sample": f"residual of the GPU solution in both coupled equations: {napply} layer applies (Laplace "
+                      f"DL-subtracted, Laplace SL, Stokes DL-subtracted, Stokes SL of -p n and of the slip traction) "
+                      f"on {len(t)} of {S.N} target "
+                      f"rows x all {S.N} sources, FP64, {dt:.1f} s"}
+    return base, resid
 
 
 def kernel_source_digest() -> str:
@@ -173,7 +199,18 @@ def main() -> int:
         wl = (f"sphere perturbed by degree<=8 real harmonics (N(0,0.05^2) coefficients, seed 0), h=1/128 "
               f"(N={S.N}), delta=3h, U={np.round(E, 4).tolist()}, mu=1, K=1e-3, alpha=1")
     delta = 3 * h
-    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), delta)
+    xd, nd, wd = dev(S.x), dev(S.n), dev(S.w)
+    # step a1 (staging: Morton sort, padded copies, tile boxes, near masks) runs
+    # once per surface, outside the solve; timed here on its own (median of 3)
+    stage_ms = []
+    for _ in range(4):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = sd.Plan(xd, nd, wd, delta)
+        torch.cuda.synchronize()
+        stage_ms.append(1e3 * (time.perf_counter() - t0))
+        plan.close()
+    plan = sd.Plan(xd, nd, wd, delta)
     opts_mixed = dict(prec="mixed", outer="gmres", tol_gmres=1e-10, tol_ddm=1e-8)
     opts_fp64 = dict(prec="fp64", outer="gmres", tol_gmres=1e-10, tol_ddm=1e-8)
     flow = lambda D: float(np.dot(D, E))
@@ -238,36 +275,43 @@ def main() -> int:
         "drag_exact": D_exact,
         "drag_rel_err_mixed": None if D_exact is None else abs(D_mixed - D_exact) / D_exact,
         "mixed_info": infos[-1],
+        "stage_ms": float(np.median(stage_ms[1:])),
     }
 
     if not args.no_fp64:
         # the FP64 baselines at their best: with and without the recycled
-        # deflation space, the faster of the two (after a warm-up solve each)
+        # deflation space, each the median of 3 timed solves after a warm-up,
+        # the faster of the two
         def best_fp64(extra):
             best = None
             for rc in (1, 0):
                 o = dict(opts_fp64, recycle=rc, **extra)
                 sd.ddm_solve(plan, mu, K, alpha, E, None, opts=o)
                 torch.cuda.synchronize()
-                t0 = time.perf_counter()
-                out = sd.ddm_solve(plan, mu, K, alpha, E, None, opts=o)
-                torch.cuda.synchronize()
-                t = time.perf_counter() - t0
+                times = []
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    out = sd.ddm_solve(plan, mu, K, alpha, E, None, opts=o)
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                t = float(np.median(times))
                 if best is None or t < best[0]:
-                    best = (t, out, rc)
+                    best = (t, out, rc, times)
             return best
-        t64, (p64, u64, D64, info64), rc64 = best_fp64({})
-        t64s, (_, _, D64s, info64s), rc64s = best_fp64({"relax_outer": 0})
+        t64, (p64, u64, D64, info64), rc64, times64 = best_fp64({})
+        t64s, (_, _, D64s, info64s), rc64s, times64s = best_fp64({"relax_outer": 0})
         result.update({
             "fp64_recycle": rc64,
             "fp64_strict_recycle": rc64s,
             "fp64_strict_ms_per_solve": 1e3 * t64s,
+            "fp64_strict_ms_samples": [1e3 * v for v in times64s],
             "speedup_mixed_vs_fp64_strict": t64s / (wall / args.steps),
             "drag_fp64_strict": flow(D64s),
             "fp64_strict_info": info64s,
         })
         result.update({
             "fp64_ms_per_solve": 1e3 * t64,
+            "fp64_ms_samples": [1e3 * v for v in times64],
             "fp64_pairs_per_s": info64["pairs"] / t64,
             "speedup_mixed_vs_fp64": t64 / (wall / args.steps),
             "drag_fp64": flow(D64),
@@ -279,7 +323,9 @@ def main() -> int:
         })
 
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = cpu_baseline(S, delta)
+        base, resid = cpu_baseline(S, delta, (mu, K, alpha), np.asarray(E), p.cpu().numpy(), u.cpu().numpy())
+        result["cpu_baseline"] = base
+        result["oracle_residual_mixed"] = resid
     plan.close()
     print(json.dumps(result), flush=True)
     return 0

@@ -147,7 +147,7 @@ void sdbie_default_opts(sdbie_opts* o);
 
 /* Bytes of device workspace a plan for n nodes (1 <= n <= 2^23) and GMRES
  * restart length up to max_restart (1..1000) needs (0 if the arguments are
- * invalid).  Roughly (88 max_restart + 1105 + 96 S) n bytes plus
+ * invalid).  Roughly (120 max_restart + 1161 + 96 S) n bytes plus
  * (n/256)^2 * 2, with S the source splits of a pair pass (a multiple of 8
  * up to 64: 64 at n = 4096, 16 at n = 68166, 8 from n = 131072 on). */
 size_t sdbie_workspace_bytes(int64_t n, int max_restart);
@@ -219,6 +219,32 @@ int ddm_adjoint(sdbie_plan plan, const sdbie_params* prm, const double U[3], con
                 const double* p, const double* u, const double dJ_ddrag[3], double* dJ_dx,
                 double* dJ_dlogK, double* dJ_dalpha, const sdbie_opts* opts, sdbie_info* info,
                 void* stream);
+
+/* Spectrum of the Dirichlet-Neumann iteration (section "Discrete iteration
+ * operator", eqs. (Discrete_iter_oper), (A_mat)).  With no far-field flow
+ * the D-N map is linear, T_lin(v) = u(p(v)).n: p the Darcy solution for the
+ * normal velocity v (weighted mean removed), u the Stokes solution for the
+ * traction -p n (with the implicit slip term when prm->alpha > 0).  The
+ * relaxed iteration's matrix is A~ = (1 - theta) I + theta T_lin, so its
+ * eigenvalues are 1 - theta + theta lambda for the eigenvalues lambda of
+ * T_lin.  m Arnoldi steps on T_lin from v0 (device [n], caller order,
+ * nonzero), each product one Darcy and one Stokes solve to opts->tol_gmres
+ * with opts->prec pairs (1 <= m <= the plan's max_restart); the Ritz values
+ * (eigenvalues of the Hessenberg matrix, by the Francis QR iteration on the
+ * host) approximate the eigenvalues of largest modulus first.  eig_re,
+ * eig_im: host double[k] (1 <= k <= m) receive the k Ritz values of largest
+ * modulus in decreasing modulus (NaN past the steps taken when the Krylov
+ * space becomes invariant; info->ddm_iters = steps taken).  Returns
+ * NOT_CONVERGED if a local solve missed its tolerance. */
+int ddm_dn_spectrum(sdbie_plan plan, const sdbie_params* prm, const double* v0, int m, int k, double* eig_re,
+                    double* eig_im, const sdbie_opts* opts, sdbie_info* info, void* stream);
+
+/* Eigenvalues of an upper Hessenberg matrix H (host, n x n, row-major; the
+ * entries below the subdiagonal are ignored) by the Francis double-shift QR
+ * iteration, the host step of ddm_dn_spectrum: eig_re, eig_im (host
+ * double[n]) in no particular order, complex pairs adjacent.  ERR_DEVICE if
+ * the iteration stalls. */
+int sdbie_hessenberg_eigenvalues(int n, const double* H, double* eig_re, double* eig_im);
 
 /* Kernel timing (diagnostics).  While enabled, every pair-sum kernel launch
  * records a HIP event pair around the kernel on the stream it runs on.

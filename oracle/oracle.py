@@ -499,6 +499,73 @@ def coupled_dense_solve(geo: Geometry, prm: Params, U, f_extra=None, return_pt=F
     return out + (z[:N],) if return_pt else out
 
 
+def coupled_residual(geo: Geometry, prm: Params, U, p, u, targets=None, f_extra=None, v=None):
+    """Residual of a computed solution (p, u) in the two equations of the D-N
+    fixed point, at the target rows (all nodes when targets is None).
+
+    Darcy, eq. (Darcy_final) with b_D = -S_L[g], g = -(mu/K) v:
+        r1 = A_D p - b1,   b1 = (mu/K) S_L[v],   v = u.n (the interface condition) unless given.
+      p is the pressure with its weighted mean removed; A_D annihilates
+      constants, so at the exact fixed point r1 is the constant -(weighted mean
+      of the completed solution): only r1 minus a constant measures an error.
+    Stokes, eq. (Stokes_final) with the traction of eq. (f), slip implicit:
+        r2 = A_S u + (sum_j w_j n_j.u_j / |S|) n + V[beta P_tau u] - b2,
+        b2 = U - V[-p n + f_extra].
+    Returns (r1 [nt], b1 [nt], r2 [3, nt], b2 [3, nt]); b1 and b2 are the
+    right-hand sides at the rows (the scales of the two residuals).
+    """
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    if v is None:
+        v = (geo.n * u).sum(axis=0)
+    b1 = (prm.mu / prm.K) * laplace_apply(geo, LSL, np.ascontiguousarray(v, dtype=np.float64), targets)
+    r1 = laplace_apply(geo, LDLS, p, targets) - b1
+    f0 = -p[None, :] * geo.n + (0.0 if f_extra is None else f_extra)
+    b2 = np.asarray(U, dtype=np.float64).reshape(3, 1) - stokes_apply(geo, prm.mu, SSL, np.ascontiguousarray(f0),
+                                                                      targets)
+    flux = float((geo.w * (geo.n * u).sum(axis=0)).sum()) / geo.area
+    nt = geo.n if targets is None else geo.n[:, np.asarray(targets)]
+    r2 = stokes_apply(geo, prm.mu, SDLS, u, targets) + flux * nt - b2
+    if prm.beta != 0.0:
+        r2 = r2 + stokes_apply(geo, prm.mu, SSL, np.ascontiguousarray(prm.beta * tangential(geo.n, u)), targets)
+    return r1, b1, r2, b2
+
+
+def dn_iteration_matrix(geo: Geometry, mu: float, K: float, theta: float) -> np.ndarray:
+    """Eq. (A_mat), the matrix of one relaxed Dirichlet-Neumann step (section
+    "Discrete iteration operator": no far-field flow, gamma = 0):
+        A~ = I - theta { I + (mu/K) [(I/2 - K~)^-1 M~_n] . n [(I/2 - H~)^-1 L~] },
+    dense, in this oracle's conventions: I/2 - H~ is the completed A_D and
+    I/2 - K~ the completed A_S (their null vectors removed by the rank-one
+    terms), L~ q is the Darcy right-hand side -S_L[q] of a flux q (b_D = -S_L[g]
+    with g = (mu/K) q), the Darcy solution has its weighted mean removed
+    (Pi), M~_n p = V[p n] and ". n" takes the normal component."""
+    N = geo.N
+    AD = laplace_matrix(geo, LDLS) + np.outer(np.ones(N), geo.w) / geo.area
+    SL = laplace_matrix(geo, LSL)
+    AS = stokes_matrix(geo, mu, SDLS)
+    AS += np.outer(geo.n.reshape(-1), (geo.w[None, :] * geo.n).reshape(-1)) / geo.area
+    V = stokes_matrix(geo, mu, SSL)
+    Nrm = np.zeros((N, 3 * N))
+    Nhat = np.zeros((3 * N, N))
+    for a in range(3):
+        Nrm[np.arange(N), a * N + np.arange(N)] = geo.n[a]
+        Nhat[a * N + np.arange(N), np.arange(N)] = geo.n[a]
+    Pi = np.eye(N) - np.outer(np.ones(N), geo.w) / geo.area
+    darcy = Pi @ np.linalg.solve(AD, -SL)          # (I/2 - H~)^-1 L~
+    stokes = Nrm @ np.linalg.solve(AS, V @ Nhat)   # [(I/2 - K~)^-1 M~_n] . n
+    return np.eye(N) - theta * (np.eye(N) + (mu / K) * (stokes @ darcy))
+
+
+def dn_iteration_eigenvalues(geo: Geometry, mu: float, K: float, theta: float, k: int = 50) -> np.ndarray:
+    """The k eigenvalues of A~ (eq. A_mat) farthest from 1 - theta, the value the
+    eigenvalues of the high harmonics cluster at (section "Discrete iteration
+    operator", figure of its eigenvalues), in that order (complex)."""
+    lam = np.linalg.eigvals(dn_iteration_matrix(geo, mu, K, theta))
+    order = np.argsort(-np.abs(lam - (1.0 - theta)), kind="stable")
+    return lam[order[:k]]
+
+
 def coupled_dense_adjoint(geo: Geometry, prm: Params, U, dJ_dD, f_extra=None):
     """Gradient of J = dJ_dD . drag by the adjoint of the coupled system.
 

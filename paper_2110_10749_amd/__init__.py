@@ -4,9 +4,10 @@ The compute path is the HIP library libsdbie.so (C ABI in include/sdbie.h);
 this package is its ctypes binding.  See `binding` for the call surface.
 """
 from .binding import (  # noqa: F401
-    ddm_adjoint,
+    ddm_adjoint, ddm_dn_spectrum, hessenberg_eigenvalues,
     DL_RAW, DL_SUB, FP64, MIXED, SL, Plan, SdbieError, darcy_solve, ddm_solve, default_opts,
-    laplace_layer_apply, lib, profile_enable, profile_read, stokes_layer_apply, stokes_solve,
+    laplace_layer_apply, lib, profile_enable, profile_read, stokes_layer_apply,
+    stokes_solve,
     workspace_bytes,
 )
 from .autograd import DragFn, drag  # noqa: F401,E402

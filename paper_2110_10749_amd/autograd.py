@@ -19,12 +19,22 @@ import torch
 from . import binding as B
 
 
+def _restart_of(opts) -> int:
+    if opts is None:
+        return 50
+    if isinstance(opts, dict):
+        return int(opts.get("restart", 50))
+    return int(opts.restart)
+
+
 class DragFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, log_K, alpha, nrm, w, delta, mu, U, f_extra=None, opts=None):
         K = float(torch.exp(log_K.detach()).item())
         a = float(alpha.detach().item())
-        plan = B.Plan(x.detach().contiguous(), nrm.detach().contiguous(), w.detach().contiguous(), float(delta))
+        # the plan's Krylov space must hold the requested restart length
+        plan = B.Plan(x.detach().contiguous(), nrm.detach().contiguous(), w.detach().contiguous(), float(delta),
+                      max_restart=max(50, _restart_of(opts)))
         p, u, D, info = B.ddm_solve(plan, mu, K, a, U, f_extra, opts)
         if not info["converged"]:
             raise B.SdbieError(B.NOT_CONVERGED, "forward ddm_solve did not converge")

@@ -100,6 +100,11 @@ def lib():
         L.ddm_adjoint.argtypes = [vp, ctypes.POINTER(Params), ctypes.POINTER(d), vp, vp, vp, ctypes.POINTER(d), vp,
                                   ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(Opts), ctypes.POINTER(Info), vp]
         L.ddm_adjoint.restype = i32
+        L.ddm_dn_spectrum.argtypes = [vp, ctypes.POINTER(Params), vp, i32, i32, ctypes.POINTER(d),
+                                      ctypes.POINTER(d), ctypes.POINTER(Opts), ctypes.POINTER(Info), vp]
+        L.ddm_dn_spectrum.restype = i32
+        L.sdbie_hessenberg_eigenvalues.argtypes = [i32, ctypes.POINTER(d), ctypes.POINTER(d), ctypes.POINTER(d)]
+        L.sdbie_hessenberg_eigenvalues.restype = i32
         L.sdbie_last_error.argtypes = []
         L.sdbie_last_error.restype = ctypes.c_char_p
         L.sdbie_abi_version.argtypes = []
@@ -305,3 +310,23 @@ def ddm_adjoint(plan: Plan, mu, K, alpha, U, p, u, dJ_ddrag, f_extra=None, opts=
                                   ctypes.byref(gK), ctypes.byref(ga), ctypes.byref(o), ctypes.byref(info),
                                   _stream(plan.device)))
     return gx, gK.value, ga.value, info.as_dict(st)
+
+
+def ddm_dn_spectrum(plan: Plan, mu, K, alpha, v0, m: int, k: int, opts=None):
+    """Ritz values of the linear D-N map after m Arnoldi steps from v0 (device (N,)):
+    returns (k complex values in decreasing modulus, info dict)."""
+    v0 = _dev(v0, (plan.n,), "v0")
+    re, im = (ctypes.c_double * k)(), (ctypes.c_double * k)()
+    prm, o, info = _params(mu, K, alpha), _opts(opts), Info()
+    st = _check(lib().ddm_dn_spectrum(plan.handle, ctypes.byref(prm), _ptr(v0), int(m), int(k), re, im,
+                                      ctypes.byref(o), ctypes.byref(info), _stream(plan.device)))
+    return [complex(re[i], im[i]) for i in range(k)], info.as_dict(st)
+
+
+def hessenberg_eigenvalues(H):
+    """Eigenvalues (complex list) of the upper Hessenberg matrix H (host, n x n nested sequence or array)."""
+    n = len(H)
+    flat = (ctypes.c_double * (n * n))(*[float(H[i][j]) for i in range(n) for j in range(n)])
+    re, im = (ctypes.c_double * n)(), (ctypes.c_double * n)()
+    _check(lib().sdbie_hessenberg_eigenvalues(n, flat, re, im))
+    return [complex(re[i], im[i]) for i in range(n)]

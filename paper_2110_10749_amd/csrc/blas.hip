@@ -84,8 +84,8 @@ __global__ void k_multi_axpy(const double* __restrict__ V, int64_t ld, int k, co
     w[i] += sign * s;
 }
 
-__global__ void k_axpby(double a, const double* __restrict__ x, double b, const double* __restrict__ y,
-                        double* __restrict__ out, int64_t len) {
+// out may alias x or y (elementwise: each lane reads its element before writing it)
+__global__ void k_axpby(double a, const double* x, double b, const double* y, double* out, int64_t len) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= len) return;
     out[i] = a * x[i] + (y ? b * y[i] : 0.0);

@@ -1,9 +1,11 @@
 // C ABI of the library: argument checks, workspace layout, plans, and the
 // conversion between the caller's node order and the staged (Morton) order.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "solver.h"
 
@@ -27,14 +29,11 @@ struct Layout {
         basis_in, basis_out, image_out, basis_rc, total;
 };
 
-Layout layout(int64_t n, int m) {
-    Layout L;
-    size_t off = 0;
-    auto take = [&](size_t bytes) {
-        const size_t o = off;
-        off = align256(off + bytes);
-        return o;
-    };
+// the node data, staging and pair-pass scratch every plan holds: nsplit
+// source splits with up to `comps` components per partial slot, m the
+// longest GMRES restart the reduction buffer serves
+template <class Take>
+void layout_common(Layout& L, Take& take, int64_t n, int m, int nsplit, int comps) {
     const size_t d = sizeof(double), f = sizeof(float);
     L.x = take(3 * n * d);
     L.nrm = take(3 * n * d);
@@ -51,14 +50,26 @@ Layout layout(int64_t n, int m) {
     L.mask32 = take(nt * nt);
     L.perm = take(n * sizeof(int32_t));
     L.keys = take(next_pow2(n) * sizeof(uint64_t));
-    L.partial = take((size_t)2 * choose_splits(n) * 6 * n * d);  // up to six components per pass
+    L.partial = take((size_t)2 * nsplit * comps * n * d);
     L.rec = take((size_t)npad * kRecBytes);
     L.red = take((size_t)kRedBlocks * (m + 2) * d);
     L.scal = take((size_t)(kScalGmres + 6 * (m + 2) + 64 > 1024 ? kScalGmres + 6 * (m + 2) + 64 : 1024) * d);
+}
+
+Layout layout(int64_t n, int m) {
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    const size_t d = sizeof(double);
+    layout_common(L, take, n, m, choose_splits(n), 6);  // up to six components per pass (adjoint)
     L.vecs = take((size_t)kNumVec * 3 * n * d);
     L.basis_in = take((size_t)(m + 1) * 3 * n * d);
     L.basis_out = take((size_t)(m + 1) * n * d);
-    L.image_out = take((size_t)(m + 1) * 4 * n * d);
+    L.image_out = take((size_t)(m + 1) * kImageStride * n * d);
     L.basis_rc = take((size_t)(m + 1) * 3 * n * d);
     L.total = off;
     return L;
@@ -127,13 +138,7 @@ hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 bool is_zero(Ctx& c, const double* a, int64_t len) { return c.norm(a, len) == 0.0; }
 
-}  // namespace
-
-size_t workspace_bytes(int64_t n, int max_restart) { return layout(n, max_restart).total; }
-
-void carve_workspace(Plan& P, void* ws) {
-    const Layout L = layout(P.n, P.max_restart);
-    char* b = static_cast<char*>(ws);
+void carve_common(Plan& P, const Layout& L, char* b) {
     P.x = reinterpret_cast<double*>(b + L.x);
     P.nrm = reinterpret_cast<double*>(b + L.nrm);
     P.w = reinterpret_cast<double*>(b + L.w);
@@ -155,11 +160,66 @@ void carve_workspace(Plan& P, void* ws) {
     P.rec = b + L.rec;
     P.red = reinterpret_cast<double*>(b + L.red);
     P.scal = reinterpret_cast<double*>(b + L.scal);
+}
+
+}  // namespace
+
+size_t workspace_bytes(int64_t n, int max_restart) { return layout(n, max_restart).total; }
+
+void carve_workspace(Plan& P, void* ws) {
+    const Layout L = layout(P.n, P.max_restart);
+    char* b = static_cast<char*>(ws);
+    carve_common(P, L, b);
+    P.nsplit = choose_splits(P.n);
+    P.max_comps = 6;
     P.vecs = reinterpret_cast<double*>(b + L.vecs);
     P.basis_in = reinterpret_cast<double*>(b + L.basis_in);
     P.basis_out = reinterpret_cast<double*>(b + L.basis_out);
     P.image_out = reinterpret_cast<double*>(b + L.image_out);
     P.basis_rc = reinterpret_cast<double*>(b + L.basis_rc);
+}
+
+void apply_laplace_layer(Plan& P, sdbie_layer layer, const double* dens, double* out, sdbie_precision prec,
+                         hipStream_t st, double* in) {
+    if (!dens || !out) fail(SDBIE_ERR_ARG, "null density or output");
+    if (dens == out) fail(SDBIE_ERR_ARG, "output aliases the density");
+    if (prec != SDBIE_FP64 && prec != SDBIE_MIXED) fail(SDBIE_ERR_ARG, "bad precision");
+    PassDesc d;
+    switch (layer) {
+        case SDBIE_SL: d.sl = true; d.c_sl = -1.0 / (4.0 * kPi); d.sl_dens = in; break;
+        case SDBIE_DL_RAW: d.dl = true; d.c_dl = -1.0 / (4.0 * kPi); d.dl_dens = in; break;
+        case SDBIE_DL_SUB: d.dl = true; d.sub = true; d.c_dl = 1.0 / (4.0 * kPi); d.dl_dens = in; break;
+        default: fail(SDBIE_ERR_ARG, "bad layer");
+    }
+    dev_gather(P, dens, in, 1, st);
+    d.mixed = prec == SDBIE_MIXED;
+    d.out = out;
+    d.scatter = true;
+    launch_laplace_pass(P, d, st);
+}
+
+void apply_stokes_layer(Plan& P, double mu, sdbie_layer layer, const double* dens, double* out,
+                        sdbie_precision prec, hipStream_t st, double* in) {
+    if (!dens || !out) fail(SDBIE_ERR_ARG, "null density or output");
+    if (dens == out) fail(SDBIE_ERR_ARG, "output aliases the density");
+    if (prec != SDBIE_FP64 && prec != SDBIE_MIXED) fail(SDBIE_ERR_ARG, "bad precision");
+    PassDesc d;
+    switch (layer) {
+        case SDBIE_SL:
+            check_finite_pos(mu, "mu");
+            d.sl = true; d.c_sl = 1.0 / (8.0 * kPi * mu); d.sl_dens = in;
+            break;
+        case SDBIE_DL_RAW: d.dl = true; d.c_dl = -3.0 / (4.0 * kPi); d.dl_dens = in; break;
+        case SDBIE_DL_SUB:
+            d.dl = true; d.sub = true; d.c_dl = -3.0 / (4.0 * kPi); d.dl_dens = in; d.base = in;
+            break;
+        default: fail(SDBIE_ERR_ARG, "bad layer");
+    }
+    dev_gather(P, dens, in, 3, st);
+    d.mixed = prec == SDBIE_MIXED;
+    d.out = out;
+    d.scatter = true;
+    launch_stokes_pass(P, d, st);
 }
 
 }  // namespace sdbie
@@ -238,23 +298,7 @@ int laplace_layer_apply(sdbie_plan plan, sdbie_layer layer, const double* dens, 
                         void* stream) {
     return guarded([&]() -> int {
         Plan& P = plan_of(plan);
-        if (!dens || !out) fail(SDBIE_ERR_ARG, "null density or output");
-        if (dens == out) fail(SDBIE_ERR_ARG, "output aliases the density");
-        if (prec != SDBIE_FP64 && prec != SDBIE_MIXED) fail(SDBIE_ERR_ARG, "bad precision");
-        hipStream_t st = stream_of(stream);
-        double* in = P.vec(kVecIn);
-        dev_gather(P, dens, in, 1, st);
-        PassDesc d;
-        d.mixed = prec == SDBIE_MIXED;
-        d.out = out;
-        d.scatter = true;
-        switch (layer) {
-            case SDBIE_SL: d.sl = true; d.c_sl = -1.0 / (4.0 * kPi); d.sl_dens = in; break;
-            case SDBIE_DL_RAW: d.dl = true; d.c_dl = -1.0 / (4.0 * kPi); d.dl_dens = in; break;
-            case SDBIE_DL_SUB: d.dl = true; d.sub = true; d.c_dl = 1.0 / (4.0 * kPi); d.dl_dens = in; break;
-            default: fail(SDBIE_ERR_ARG, "bad layer");
-        }
-        launch_laplace_pass(P, d, st);
+        apply_laplace_layer(P, layer, dens, out, prec, stream_of(stream), P.vec(kVecIn));
         return SDBIE_OK;
     });
 }
@@ -263,28 +307,7 @@ int stokes_layer_apply(sdbie_plan plan, double mu, sdbie_layer layer, const doub
                        sdbie_precision prec, void* stream) {
     return guarded([&]() -> int {
         Plan& P = plan_of(plan);
-        if (!dens || !out) fail(SDBIE_ERR_ARG, "null density or output");
-        if (dens == out) fail(SDBIE_ERR_ARG, "output aliases the density");
-        if (prec != SDBIE_FP64 && prec != SDBIE_MIXED) fail(SDBIE_ERR_ARG, "bad precision");
-        hipStream_t st = stream_of(stream);
-        double* in = P.vec(kVecIn);
-        dev_gather(P, dens, in, 3, st);
-        PassDesc d;
-        d.mixed = prec == SDBIE_MIXED;
-        d.out = out;
-        d.scatter = true;
-        switch (layer) {
-            case SDBIE_SL:
-                check_finite_pos(mu, "mu");
-                d.sl = true; d.c_sl = 1.0 / (8.0 * kPi * mu); d.sl_dens = in;
-                break;
-            case SDBIE_DL_RAW: d.dl = true; d.c_dl = -3.0 / (4.0 * kPi); d.dl_dens = in; break;
-            case SDBIE_DL_SUB:
-                d.dl = true; d.sub = true; d.c_dl = -3.0 / (4.0 * kPi); d.dl_dens = in; d.base = in;
-                break;
-            default: fail(SDBIE_ERR_ARG, "bad layer");
-        }
-        launch_stokes_pass(P, d, st);
+        apply_stokes_layer(P, mu, layer, dens, out, prec, stream_of(stream), P.vec(kVecIn));
         return SDBIE_OK;
     });
 }
@@ -386,6 +409,53 @@ int ddm_adjoint(sdbie_plan plan, const sdbie_params* prm, const double U[3], con
         c.finish();
         if (info) *info = c.info;
         return c.converged ? SDBIE_OK : SDBIE_NOT_CONVERGED;
+    });
+}
+
+int ddm_dn_spectrum(sdbie_plan plan, const sdbie_params* prm, const double* v0, int m, int k, double* eig_re,
+                    double* eig_im, const sdbie_opts* opts, sdbie_info* info, void* stream) {
+    return guarded([&]() -> int {
+        Plan& P = plan_of(plan);
+        check_params(prm);
+        if (!v0 || !eig_re || !eig_im) fail(SDBIE_ERR_ARG, "null start vector or eigenvalue array");
+        if (m < 1 || m > P.max_restart) fail(SDBIE_ERR_ARG, "m must lie in [1, max_restart of the plan]");
+        if (k < 1 || k > m) fail(SDBIE_ERR_ARG, "k must lie in [1, m]");
+        const sdbie_opts o = checked_opts(opts, P);
+        if (o.slip != 0 && prm->alpha != 0.0) fail(SDBIE_ERR_ARG, "the D-N map is linear with implicit slip only");
+        Ctx c(P, stream_of(stream), o);
+        double* v = P.vec(kVecIn);
+        dev_gather(P, v0, v, 1, c.s);
+        std::vector<double> H;
+        const int used = c.dn_arnoldi(*prm, v, m, H);
+        std::vector<double> A((size_t)used * used), wr(used), wi(used);
+        for (int i = 0; i < used; ++i)
+            for (int j = 0; j < used; ++j) A[(size_t)i * used + j] = H[(size_t)i * m + j];
+        if (!hessenberg_eigenvalues(used, A.data(), wr.data(), wi.data()))
+            fail(SDBIE_ERR_DEVICE, "the Hessenberg QR iteration did not converge");
+        std::vector<int> order(used);
+        for (int i = 0; i < used; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return std::hypot(wr[a], wi[a]) > std::hypot(wr[b], wi[b]); });
+        for (int i = 0; i < k; ++i) {
+            eig_re[i] = i < used ? wr[order[i]] : NAN;
+            eig_im[i] = i < used ? wi[order[i]] : NAN;
+        }
+        c.info.ddm_iters = used;
+        c.finish();
+        if (info) *info = c.info;
+        return c.converged ? SDBIE_OK : SDBIE_NOT_CONVERGED;
+    });
+}
+
+int sdbie_hessenberg_eigenvalues(int n, const double* H, double* eig_re, double* eig_im) {
+    return guarded([&]() -> int {
+        if (n < 1 || !H || !eig_re || !eig_im) fail(SDBIE_ERR_ARG, "bad Hessenberg eigenvalue arguments");
+        std::vector<double> A(H, H + (size_t)n * n);
+        for (int i = 2; i < n; ++i)
+            for (int j = 0; j < i - 1; ++j) A[(size_t)i * n + j] = 0.0;  // only the Hessenberg part is read
+        if (!hessenberg_eigenvalues(n, A.data(), eig_re, eig_im))
+            fail(SDBIE_ERR_DEVICE, "the Hessenberg QR iteration did not converge");
+        return SDBIE_OK;
     });
 }
 

@@ -125,14 +125,17 @@ struct Plan {
     uint64_t* keys = nullptr; // sort scratch, [npow2]
     int64_t npow2 = 0;
     // scratch
-    double* partial = nullptr;  // [2 * nsplit][C][n], C <= 6: far splits then near splits
+    int nsplit = 0;             // source splits of a pair pass (choose_splits(n) or fewer)
+    int max_comps = 6;          // components a pass may write per slot (the partial buffer's C)
+    double* partial = nullptr;  // [2 * nsplit][C][n], C <= max_comps: far splits then near splits
     void* rec = nullptr;        // per-pass source records, [npad][kRecBytes]
     double* red = nullptr;      // reduction partials [kRedBlocks * 64]
     double* scal = nullptr;     // small device scalars / columns [256]
     double* vecs = nullptr;     // general work vectors, kNumVec x [3][n]
     double* basis_in = nullptr;   // inner GMRES basis [(max_restart+1)][3n]
     double* basis_out = nullptr;  // outer GMRES basis [(max_restart+1)][n]
-    double* image_out = nullptr;  // local solutions (p, u) of each outer basis vector [(max_restart+1)][4n]
+    double* image_out = nullptr;  // local solutions (p, u) and right-hand sides (b_D, b_S) of each outer
+                                  // basis vector [(max_restart+1)][8n]
     double* basis_rc = nullptr;   // recycled inner basis (deflation space) [(max_restart+1)][3n]
     double* host_pinned = nullptr;  // not used (host buffers are plain)
     // (target, source) pairs of real nodes in the near tile pairs (double, float masks)
@@ -143,10 +146,17 @@ struct Plan {
     double* vec(int k) const { return vecs + (size_t)k * 3 * n; }
 };
 
-constexpr int kNumVec = 30;
+constexpr int kNumVec = 31;
+constexpr int kImageStride = 8;  // doubles per node of one image-basis slot: p, u, b_D, b_S
 
 size_t workspace_bytes(int64_t n, int max_restart);
 void carve_workspace(Plan& P, void* ws);
+// the layer sums of the C ABI on a staged plan; `in` receives the density in
+// staged order ([n] or [3][n])
+void apply_laplace_layer(Plan& P, sdbie_layer layer, const double* dens, double* out, sdbie_precision prec,
+                         hipStream_t st, double* in);
+void apply_stokes_layer(Plan& P, double mu, sdbie_layer layer, const double* dens, double* out,
+                        sdbie_precision prec, hipStream_t st, double* in);
 
 // kernels (pair_kernels.hip) ----------------------------------------------------
 void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t s);
@@ -204,5 +214,7 @@ void dev_adj_rhs(const Plan& P, const double e[3], double beta, double* gp, doub
 
 // host-side helpers
 double host_read_scalar(const double* d, hipStream_t s);
+// eigenvalues of an upper Hessenberg matrix (n x n, row-major, overwritten); false if the QR iteration stalls
+bool hessenberg_eigenvalues(int n, double* A, double* wr, double* wi);
 
 }  // namespace sdbie

@@ -30,6 +30,9 @@
 // erfcx(rho) and erfcx from a fitted polynomial (no branches inside erf);
 // beyond the cutoff every s_k equals 1 to within half an ulp of T and the
 // plain 1/r^p kernels are used.
+#include <cstdio>
+#include <cstdlib>
+
 #include "internal.h"
 #include "smoothing_coeffs.h"
 
@@ -975,13 +978,15 @@ __global__ __launch_bounds__(kTPB) void pass_pairs_wide(KArgs a) {
 
 // Sum the 2 nsplit partial slots of each target in a fixed order, then
 //   out = tw * sum + base_scale * base + comp_scale * comp[0] * (1 or n_i) + add
+// out may alias base when perm is null (each lane reads its own elements before
+// writing them).
 template <int C>
 __global__ void epilogue(int64_t n, int nslots, const double* __restrict__ partial,
                          const double* __restrict__ tw,
-                         const double* __restrict__ base, double base_scale,
+                         const double* base, double base_scale,
                          const double* __restrict__ comp, double comp_scale,
                          const double* __restrict__ nrm, double add0, double add1, double add2,
-                         double* __restrict__ out, const int32_t* __restrict__ perm) {
+                         double* out, const int32_t* __restrict__ perm) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double cs = comp ? comp_scale * comp[0] : 0.0;
@@ -1039,6 +1044,7 @@ struct family_is_gradient<GradOp<SWAP>> { static constexpr bool value = true; };
 template <class Op, typename T>
 void launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int family, int code, bool mixed) {
     static_assert(Op::R * sizeof(T) <= kRecBytes, "record larger than its workspace slot");
+    if (Op::C > P.max_comps) throw Error(SDBIE_ERR_ARG, "this workspace holds no partial slots for that pass");
     const double all = (double)P.n * (double)P.n;
     const double near = mixed ? P.near_pairs32 : P.near_pairs64;
     {
@@ -1076,6 +1082,23 @@ void launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int fami
 
 }  // namespace
 
+namespace {
+// SDBIE_DEBUG >= 3 prints every pair pass as it is enqueued (family, precision, terms)
+bool trace_passes() {
+    static const bool on = [] {
+        const char* e = std::getenv("SDBIE_DEBUG");
+        return e && std::atoi(e) >= 3;
+    }();
+    return on;
+}
+void trace(const char* family, const PassDesc& d) {
+    if (trace_passes())
+        std::fprintf(stderr, "[sdbie] pass %s %s%s%s%s%s%s\n", family, d.mixed ? "f32" : "f64", d.dl ? " dl" : "",
+                     d.sub ? " sub" : "", d.sl ? " sl" : "", d.slip_beta != 0.0 && !d.sl_dens ? " slip" : "",
+                     d.target_normal ? " transposed" : "");
+}
+}  // namespace
+
 int choose_splits(int64_t n) {
     const int64_t tblocks = (n + kTPB - 1) / kTPB;
     int64_t s = 8 * ((SDBIE_SPLIT_TARGET + 8 * tblocks - 1) / (8 * tblocks));
@@ -1087,7 +1110,8 @@ int choose_splits(int64_t n) {
 // The smoothing cutoff rho_cut of a pass is the Stokes one (the larger) for
 // both families, matching the tile masks built at staging.
 void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
-    const int S = choose_splits(P.n);
+    trace("laplace", d);
+    const int S = P.nsplit;
     const double cut = d.mixed ? (double)SDBIE_RHO_CUT_STOKES_F32 : SDBIE_RHO_CUT_STOKES_F64;
     const KArgs a = make_args(P, d, S, cut);
     const int code = (d.dl ? 1 : 0) | (d.sl ? 2 : 0) | (d.sub ? 4 : 0);
@@ -1132,7 +1156,8 @@ void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
 }
 
 void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
-    const int S = choose_splits(P.n);
+    trace("stokes", d);
+    const int S = P.nsplit;
     const double cut = d.mixed ? (double)SDBIE_RHO_CUT_STOKES_F32 : SDBIE_RHO_CUT_STOKES_F64;
     const KArgs a = make_args(P, d, S, cut);
     const bool slip = d.sl && d.slip_beta != 0.0 && d.sl_dens == nullptr;
@@ -1195,7 +1220,7 @@ void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
 }
 
 void launch_grad_pass(const Plan& P, const GradDesc& g, hipStream_t st) {
-    const int S = choose_splits(P.n);
+    const int S = P.nsplit;
     PassDesc d;
     KArgs a = make_args(P, d, S, SDBIE_RHO_CUT_STOKES_F64);
     a.g_p = g.p;

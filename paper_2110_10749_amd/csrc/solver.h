@@ -2,6 +2,7 @@
 #pragma once
 
 #include <functional>
+#include <vector>
 
 #include "internal.h"
 
@@ -35,8 +36,9 @@ enum : int {
     kVecCoupledDP,    // mixed coupled refinement: pressure correction
     kVecCoupledDU,    // mixed coupled refinement: velocity correction
     kVecCoupledV,     // mixed coupled refinement: u.n / projected pressure
-    kVecImage,        // interface solve: (p, u) combined from the image basis (4n: two slots)
+    kVecImage,        // interface solve: (p, u, b_D, b_S) combined from the image basis (8n: three slots)
     kVecImage2,
+    kVecImage3,
     kVecRecycle,      // device coefficients of the deflation corrections
     kVecSpare,
 };
@@ -125,20 +127,31 @@ struct Ctx {
     // residual estimate of the iteration the product belongs to (0 for true
     // residuals, which need full accuracy)
     using GmresOp = std::function<void(const double*, double*, bool, double)>;
+    // r = b - A x in double pairs, from one fused pass (the right-hand side's
+    // single layer and the operator's double layer together); replaces the
+    // separate right-hand-side pass of a warm-started solve
+    using ResidualFn = std::function<void(const double*, double*)>;
     static constexpr double kAllFloat = __builtin_huge_val();
+    // with res set, b is not read: residuals come from res, and bnorm (an
+    // estimate of ||b|| good to a few digits) scales the tolerance
     GmresOut gmres(const GmresWS& ws, const GmresOp& op, const double* b, double* x, int64_t L, bool x_nonzero,
-                   double tol, int restart, int maxit, double relax = 0.0);
+                   double tol, int restart, int maxit, double relax = 0.0, const ResidualFn* res = nullptr,
+                   double bnorm = 0.0);
     void solve(const std::function<void(const double*, double*, bool)>& op, const double* b, double* x, int64_t L,
-               bool x_nonzero, double* rbuf, double* cbuf);
+               bool x_nonzero, double* rbuf, double* cbuf, const ResidualFn* res = nullptr, double bnorm = 0.0);
 
     // v_zero: v is known to be zero (then, without an extra right-hand side,
-    // b = 0 and its single-layer pass is skipped)
+    // b = 0 and its single-layer pass is skipped).  bnorm > 0 (with a warm
+    // start p, no extra right-hand side): an estimate of ||b||; the residuals
+    // then come from one fused pass each and b itself is never formed
     void darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonzero, const double* extra_rhs,
-               bool remove_mean = true, bool v_zero = false);
+               bool remove_mean = true, bool v_zero = false, double bnorm = 0.0);
     // p_zero: p is known to be zero (then, without fx or lagged slip, the
-    // right-hand side is U itself and its single-layer pass is skipped)
+    // right-hand side is U itself and its single-layer pass is skipped).
+    // bnorm: as for darcy()
     void stokes(const sdbie_params& prm, const double U[3], const double* p, const double* fx, double* u,
-                bool u_nonzero, const double* extra_rhs, bool p_zero = false);
+                bool u_nonzero, const double* extra_rhs, bool p_zero = false, double bnorm = 0.0);
+    bool fused_residuals_ok(bool warm, const double* extra_rhs, double bnorm) const;
     void ddm(const sdbie_params& prm, const double U[3], const double* fx, double* p, double* u, double drag[3]);
     void ddm_outer(const sdbie_params& prm, const double U[3], const double* fx, const double* r1, const double* r2,
                    double* p, double* u, bool remove_mean, double tol);
@@ -149,6 +162,8 @@ struct Ctx {
     void adjoint(const sdbie_params& prm, const double U[3], const double* fx, const double* p, const double* u,
                  const double e[3], double* grad, double* dlogK, double* dalpha);
     void compute_drag(const sdbie_params& prm, const double* p, const double* u, const double* fx, double drag[3]);
+    // Arnoldi on the linear D-N map (spectrum.hip)
+    int dn_arnoldi(const sdbie_params& prm, const double* v0, int m, std::vector<double>& H);
 };
 
 }  // namespace sdbie

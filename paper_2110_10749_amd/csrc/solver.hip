@@ -124,9 +124,9 @@ void Ctx::single_layer_stokes(const double* f, double mu, double scale, const do
 // grow as the residual shrinks), and a cycle that used float pairs ends with
 // a double-pair true residual, which alone decides convergence.
 GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, double* x, int64_t L, bool x_nonzero,
-                    double tol, int restart, int maxit, double relax) {
+                    double tol, int restart, int maxit, double relax, const ResidualFn* resfn, double bnorm_in) {
     GmresOut res;
-    const double bnorm = norm(b, L);
+    const double bnorm = resfn ? bnorm_in : norm(b, L);
     if (bnorm == 0.0) {
         dev_fill(0.0, x, L, s);
         res.conv = true;
@@ -135,7 +135,11 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
     double* r = ws.r;
     double* w = ws.w;
     const bool all32 = std::isinf(relax);
-    if (x_nonzero) {
+    if (resfn && !all32) {
+        if (!x_nonzero) dev_fill(0.0, x, L, s);
+        krylov_index = -1;
+        (*resfn)(x, r);
+    } else if (x_nonzero) {
         krylov_index = -1;
         op(x, r, all32, 0.0);
         dev_axpby(1.0, b, -1.0, r, r, L, s);
@@ -270,8 +274,12 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
         if (!verify && (res.relres <= tol || res.iters >= maxit)) break;
         // restart from (or verify with) the true residual
         krylov_index = -1;
-        op(x, r, all32, 0.0);
-        dev_axpby(1.0, b, -1.0, r, r, L, s);
+        if (resfn && !all32) {
+            (*resfn)(x, r);
+        } else {
+            op(x, r, all32, 0.0);
+            dev_axpby(1.0, b, -1.0, r, r, L, s);
+        }
         beta = norm(r, L);
         res.relres = beta / bnorm;
         if (verify) res.checks++;
@@ -305,7 +313,7 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
 // Solve A x = b: plain GMRES with the double-pair operator, or iterative
 // refinement (double residual, float-pair correction solves).
 void Ctx::solve(const std::function<void(const double*, double*, bool)>& op3, const double* b, double* x,
-                int64_t L, bool x_nonzero, double* rbuf, double* cbuf) {
+                int64_t L, bool x_nonzero, double* rbuf, double* cbuf, const ResidualFn* resfn, double bnorm) {
     const GmresOp op = [&](const double* in, double* out, bool m32, double) { op3(in, out, m32); };
     if (corr) {
         const bool m32 = debug_level() < 10;  // SDBIE_DEBUG >= 10: double-pair corrections (diagnostics)
@@ -315,6 +323,8 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op3, co
         return;
     }
     const double tol = tol_local > 0.0 ? tol_local : o.tol_gmres;
+    if (resfn && (o.local_solver == 1 || loose32 || (o.prec == SDBIE_MIXED && o.mixed_mode != 2)))
+        throw Error(SDBIE_ERR_ARG, "internal: a fused residual needs the GMRES local solver");
     if (o.local_solver == 1) {
         // successive approximations (eqs. Darcy_BIEM_iter, Stokes_BIEM_iter)
         // on the completed operator: x <- x + (b - A x) until the relative
@@ -352,41 +362,32 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op3, co
         // sought, so a looser local solve switches earlier: at tol_mixed for
         // tol_gmres, in proportion above it.
         const double relax = mixed ? std::min(1.0, o.tol_mixed * (tol / o.tol_gmres)) : 0.0;
-        GmresOut g = gmres(inner, op, b, x, L, x_nonzero, tol, o.restart, o.maxit_gmres, relax);
+        GmresOut g = gmres(inner, op, b, x, L, x_nonzero, tol, o.restart, o.maxit_gmres, relax, resfn, bnorm);
         if (mixed) info.refine_steps += g.checks;
         info.gmres_iters += g.iters;
         info.relres = g.relres;
         if (!g.conv) converged = false;
         return;
     }
-    const double bnorm = norm(b, L);
-    if (bnorm == 0.0) {
+    const double b_norm = norm(b, L);
+    if (b_norm == 0.0) {
         dev_fill(0.0, x, L, s);
         info.relres = 0.0;
         return;
     }
+    // every step starts from a double-pair residual, and that residual alone
+    // decides convergence (and is what info.relres reports)
     bool have_x = x_nonzero;
     int step = 0;
     double rel = 1.0;
-    double predicted = -1.0;  // residual bound after an unverified correction
     for (;; ++step) {
-        if (predicted >= 0.0) {
-            // the last correction c solved A32 c = r to tol_c; the new residual
-            // r - A64 c = (r - A32 c) + (A32 - A64) c is bounded by
-            // rel * (tol_c + ||A32 - A64|| ||A^-1||) with the float-pair
-            // operator error ~3e-7 and ||A^-1|| ~ 10 for these second-kind
-            // operators; with a factor 2 of margin, accept it without a
-            // double-pair pass
-            rel = predicted;
-            break;
-        }
         if (have_x) {
             op3(x, rbuf, false);
             dev_axpby(1.0, b, -1.0, rbuf, rbuf, L, s);
         } else {
             copy(b, rbuf, L);
         }
-        rel = norm(rbuf, L) / bnorm;
+        rel = norm(rbuf, L) / b_norm;
         if (rel <= tol || step >= o.refine_max) break;
         GmresOut g = gmres(inner, op, rbuf, cbuf, L, false, o.tol_mixed, o.restart, o.maxit_gmres, kAllFloat);
         info.gmres_iters += g.iters;
@@ -396,8 +397,6 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op3, co
             copy(cbuf, x, L);
             have_x = true;
         }
-        const double bound = 2.0 * rel * (g.relres + 5e-6);
-        if (g.conv && bound <= tol) predicted = bound;
     }
     info.refine_steps += step;
     info.relres = rel;
@@ -407,16 +406,42 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op3, co
 // ------------------------------------------------------------------------------
 // local problems
 // ------------------------------------------------------------------------------
+// whether a warm-started local solve may take its residuals from fused passes
+bool Ctx::fused_residuals_ok(bool warm, const double* extra_rhs, double bnorm) const {
+    return warm && bnorm > 0.0 && !extra_rhs && !corr && !loose32 && o.local_solver == 0 &&
+           (o.prec != SDBIE_MIXED || o.mixed_mode == 2);
+}
+
 void Ctx::darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonzero, const double* extra_rhs,
-                bool remove_mean, bool v_zero) {
+                bool remove_mean, bool v_zero, double bnorm) {
     const int64_t n = P.n;
     double* b = P.vec(kVecDarcyB);
-    // b = -S_L[g], g = dp/dn = -(mu/K) v   =>  b = (mu/K) S_L[v]
-    if (v_zero) dev_fill(0.0, b, n, s);
-    else single_layer_laplace(v, prm.mu / prm.K, b, (corr && debug_level() < 10) || loose32);
-    if (extra_rhs) dev_axpby(1.0, b, 1.0, extra_rhs, b, n, s);
-    solve([&](const double* in, double* out, bool mx) { op_darcy(in, out, mx); }, b, p, n, p_nonzero,
-          P.vec(kVecRefR), P.vec(kVecRefC));
+    const auto op = [&](const double* in, double* out, bool mx) { op_darcy(in, out, mx); };
+    if (!v_zero && fused_residuals_ok(p_nonzero, extra_rhs, bnorm)) {
+        // r = (mu/K) S_L[v] - Abar_D x: the single and subtracted double layer in one pass
+        const ResidualFn res = [&](const double* xv, double* r) {
+            dev_dot(P, P.w, xv, n, P.scal + kScalCompD, s);
+            PassDesc d;
+            d.dl = true;
+            d.sub = true;
+            d.c_dl = -1.0 / (4.0 * kPi);
+            d.dl_dens = xv;
+            d.sl = true;
+            d.c_sl = -(prm.mu / prm.K) / (4.0 * kPi);
+            d.sl_dens = v;
+            d.comp = P.scal + kScalCompD;
+            d.comp_scale = -1.0 / P.area;
+            d.out = r;
+            launch_laplace_pass(P, d, s);
+        };
+        solve(op, nullptr, p, n, true, P.vec(kVecRefR), P.vec(kVecRefC), &res, bnorm);
+    } else {
+        // b = -S_L[g], g = dp/dn = -(mu/K) v   =>  b = (mu/K) S_L[v]
+        if (v_zero) dev_fill(0.0, b, n, s);
+        else single_layer_laplace(v, prm.mu / prm.K, b, (corr && debug_level() < 10) || loose32);
+        if (extra_rhs) dev_axpby(1.0, b, 1.0, extra_rhs, b, n, s);
+        solve(op, b, p, n, p_nonzero, P.vec(kVecRefR), P.vec(kVecRefC));
+    }
     if (remove_mean) {
         dev_dot(P, P.w, p, n, P.scal + kScalMean, s);
         dev_add_scaled_scalar(p, P.scal + kScalMean, -1.0 / P.area, n, s);
@@ -424,12 +449,41 @@ void Ctx::darcy(const sdbie_params& prm, const double* v, double* p, bool p_nonz
 }
 
 void Ctx::stokes(const sdbie_params& prm, const double U[3], const double* p, const double* fx, double* u,
-                 bool u_nonzero, const double* extra_rhs, bool p_zero) {
+                 bool u_nonzero, const double* extra_rhs, bool p_zero, double bnorm) {
     const int64_t n = P.n;
     const double beta = prm.alpha * prm.mu / std::sqrt(prm.K);
     double* f = P.vec(kVecTraction);
     double* rhs = P.vec(kVecStokesB);
     const bool lagged = o.slip == 1 && beta != 0.0;
+    if (!lagged && fused_residuals_ok(u_nonzero, extra_rhs, bnorm)) {
+        // r = U - V[-p n + beta P_tau x + fx] - Abar_S x: the traction's single layer
+        // and the subtracted stresslet in one pass
+        const ResidualFn res = [&](const double* xv, double* r) {
+            dev_traction(P, p, xv, beta, fx, f, s);
+            dev_dot(P, P.wn, xv, 3 * n, P.scal + kScalCompS, s);
+            PassDesc d;
+            d.dl = true;
+            d.sub = true;
+            d.c_dl = 3.0 / (4.0 * kPi);
+            d.dl_dens = xv;
+            d.base = xv;
+            d.base_scale = -1.0;
+            d.sl = true;
+            d.c_sl = -1.0 / (8.0 * kPi * prm.mu);
+            d.sl_dens = f;
+            d.comp = P.scal + kScalCompS;
+            d.comp_scale = -1.0 / P.area;
+            d.add_const = U;
+            d.out = r;
+            launch_stokes_pass(P, d, s);
+        };
+        Recycle* saved = rc_cur;
+        if (o.recycle && !corr && o.prec == SDBIE_FP64) rc_cur = &rc_stokes;
+        solve([&](const double* in, double* out, bool mx) { op_stokes(in, out, prm.mu, beta, mx); }, nullptr, u,
+              3 * n, true, P.vec(kVecRefR), P.vec(kVecRefC), &res, bnorm);
+        rc_cur = saved;
+        return;
+    }
     if (p_zero && !fx && !lagged) {
         // zero traction: V[f] = 0, so the right-hand side is the uniform U
         for (int c = 0; c < 3; ++c) dev_fill(U[c], rhs + c * n, n, s);
@@ -522,10 +576,14 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
     double* pp = P.vec(kVecCoupledV);
     double* dv = P.vec(kVecVn);
     const bool relax = o.relax_outer != 0 && !corr;
-    // image basis: the local solutions of every interface product, combined
-    // with the GMRES coefficients into a warm start (p, u) for the final solves
+    // image basis: the local solutions and right-hand sides of every interface
+    // product, combined with the GMRES coefficients into a warm start (p, u)
+    // for the final solves and the norms of their right-hand sides (which
+    // lets those solves take their residuals from fused passes)
     const bool image = !corr;
-    double* img = P.vec(kVecImage);  // [p (n) | u (3n)]
+    static_assert(kVecImage2 == kVecImage + 1 && kVecImage3 == kVecImage + 2, "the image vector spans three slots");
+    double* img = P.vec(kVecImage);  // [p (n) | u (3n) | b_D (n) | b_S (3n)]
+    const int64_t ld_img = (int64_t)kImageStride * n;
     // t0 = T(0)
     if (r1) {
         dev_fill(0.0, v, n, s);
@@ -544,8 +602,11 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
     if (image) {
         copy(pl, img, n);  // p(0): zero without an extra Darcy right-hand side
         copy(ul, img + n, 3 * n);
+        if (r1) copy(P.vec(kVecDarcyB), img + 4 * n, n);
+        else dev_fill(0.0, img + 4 * n, n, s);
+        copy(P.vec(kVecStokesB), img + 5 * n, 3 * n);
         outer.W2 = P.image_out;
-        outer.ld2 = 4 * n;
+        outer.ld2 = ld_img;
         outer.x2 = img;
     }
     double tol_cyc = tol;  // relative tolerance of the current cycle
@@ -565,12 +626,13 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
                          ++outer_steps, rr, tol_local > 0.0 ? tol_local : o.tol_gmres,
                          loose32 ? " (float pairs)" : "");
         darcy(prm, y, pl, false, nullptr, remove_mean);
-        double* slot = image && kslot >= 0 ? P.image_out + (int64_t)kslot * 4 * n : nullptr;
+        double* slot = image && kslot >= 0 ? P.image_out + (int64_t)kslot * ld_img : nullptr;
         if (slot) {
             // the Darcy solution before its weighted mean was removed: the
             // solution of the completed equation, hence a warm start for it
             copy(pl, slot, n);
             dev_add_scaled_scalar(slot, P.scal + kScalMean, 1.0 / P.area, n, s);
+            copy(P.vec(kVecDarcyB), slot + 4 * n, n);
         }
         const double* ps = pl;
         if (!remove_mean) {
@@ -578,18 +640,24 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
             ps = pp;
         }
         stokes(prm, zero, ps, nullptr, ul, false, nullptr);
-        if (slot) copy(ul, slot + n, 3 * n);
+        if (slot) {
+            copy(ul, slot + n, 3 * n);
+            copy(P.vec(kVecStokesB), slot + 5 * n, 3 * n);
+        }
         dev_normal_component(P, ul, out, s);
         dev_axpby(1.0, y, -1.0, out, out, n, s);
         tol_local = tl_save;
         loose32 = l_save;
     };
     auto finish = [&]() {
+        double bD = 0.0, bS = 0.0;  // norms of the final right-hand sides, from the image basis
         if (image) {
             copy(img, p, n);
             copy(img + n, u, 3 * n);
+            bD = norm(img + 4 * n, n);
+            bS = norm(img + 5 * n, 3 * n);
         }
-        darcy(prm, v, p, image, r1, remove_mean);
+        darcy(prm, v, p, image, r1, remove_mean, false, bD);
         if (image) {  // keep the pre-mean-removal solution for a correction cycle
             copy(p, img, n);
             dev_add_scaled_scalar(img, P.scal + kScalMean, 1.0 / P.area, n, s);
@@ -599,7 +667,7 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
             project_mean(p, pp);
             ps = pp;
         }
-        stokes(prm, U, ps, fx, u, image, r2);
+        stokes(prm, U, ps, fx, u, image, r2, false, bS);
         if (image) copy(u, img + n, 3 * n);
     };
     GmresOut g = gmres(outer, op, t0, v, n, false, tol, o.restart, o.maxit_ddm);

@@ -107,7 +107,11 @@ __global__ void k_stage(int64_t n, const uint64_t* __restrict__ keys, const doub
 }
 
 // padded copies for the pair kernels: nodes k >= n sit at a point `far`
-// outside the bounding box (10 extents away) with zero weight and normal
+// outside the bounding box (10 extents away) with zero weight and normal.
+// The float copy is taken relative to the centre of the bounding box: the
+// kernels see coordinates only through differences x_i - x_j, and the
+// rounding of a float coordinate is then set by the body's extent, not by
+// its distance from the origin.
 __global__ void k_pad(int64_t n, int64_t npad, const double* __restrict__ xs, const double* __restrict__ ns,
                       const double* __restrict__ ws, const double* __restrict__ bb, double* __restrict__ px,
                       double* __restrict__ pn, double* __restrict__ pw, float* __restrict__ px32) {
@@ -118,7 +122,7 @@ __global__ void k_pad(int64_t n, int64_t npad, const double* __restrict__ xs, co
         const double xv = k < n ? xs[c * n + k] : bb[2 * c + 1] + 10.0 * ext + 1.0;
         px[c * npad + k] = xv;
         pn[c * npad + k] = k < n ? ns[c * n + k] : 0.0;
-        px32[c * npad + k] = (float)xv;
+        px32[c * npad + k] = (float)(xv - 0.5 * (bb[2 * c] + bb[2 * c + 1]));
     }
     pw[k] = k < n ? ws[k] : 0.0;
 }
@@ -187,8 +191,10 @@ __global__ void k_near_masks(int nt, int64_t n, const double* __restrict__ boxes
 void stage_surface(Plan& P, const sdbie_surface* s, hipStream_t st) {
     const int64_t n = P.n;
     // finite check of the node data first (Morton keys of NaN are meaningless)
+    // flags and counters are cleared by a fill kernel, not a memset node (the
+    // staging of the allocation-free entry point may sit in a captured stream)
     int* flag = reinterpret_cast<int*>(P.scal + kScalStage);
-    SDBIE_HIP(hipMemsetAsync(flag, 0, 2 * sizeof(int), st));
+    dev_fill(0.0, P.scal + kScalStage, 1, st);  // two ints
     dev_check_finite(s->x, 3 * n, kMaxCoord, flag, st);
     dev_check_finite(s->nrm, 3 * n, HUGE_VAL, flag, st);
     dev_check_finite(s->w, n, HUGE_VAL, flag, st);
@@ -227,7 +233,7 @@ void stage_surface(Plan& P, const sdbie_surface* s, hipStream_t st) {
     const double rc32 = SDBIE_RHO_CUT_STOKES_F32 * P.delta * (1.0 + 1e-6);
     const int64_t nt2 = (int64_t)P.ntiles * P.ntiles;
     unsigned long long* cnt = reinterpret_cast<unsigned long long*>(P.scal + kScalStage + 10);
-    SDBIE_HIP(hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned long long), st));
+    dev_fill(0.0, P.scal + kScalStage + 10, 2, st);  // two 64-bit counters (all-zero bits)
     hipLaunchKernelGGL(k_near_masks, dim3((unsigned)((nt2 + 255) / 256)), dim3(256), 0, st, P.ntiles, n,
                        (const double*)P.boxes, rc64, rc32, P.mask64, P.mask32, cnt);
     SDBIE_LAUNCHED();

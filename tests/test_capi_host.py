@@ -56,10 +56,10 @@ def test_workspace_bytes(L):
 
 @pytest.mark.parametrize("n,m,splits", [(4096, 50, 64), (68166, 50, 16), (68166, 1000, 16), (351866, 50, 8)])
 def test_workspace_formula_in_header(L, n, m, splits):
-    # the header's estimate (88 m + 1105 + 96 S) n + (n/256)^2 * 2, within 1%
+    # the header's estimate (120 m + 1161 + 96 S) n + (n/256)^2 * 2, within 1%
     from paper_2110_10749_amd import binding
     nt = (n + 255) // 256
-    est = (88 * m + 1105 + 96 * splits) * n + 2 * nt * nt
+    est = (120 * m + 1161 + 96 * splits) * n + 2 * nt * nt
     assert abs(est / binding.workspace_bytes(n, m) - 1.0) < 0.01
 
 
@@ -95,3 +95,63 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
     d = (ctypes.c_double * 3)()
     assert L.ddm_solve(None, ctypes.byref(prm), U, None, None, None, d, None, None, None) == B.ERR_ARG
     assert L.sdbie_plan_n(None) == -1
+
+
+def _match(a, b):
+    """Largest distance from each value of a to the nearest unused value of b."""
+    b = list(b)
+    worst = 0.0
+    for z in a:
+        j = min(range(len(b)), key=lambda i: abs(b[i] - z))
+        worst = max(worst, abs(b[j] - z))
+        b.pop(j)
+    return worst
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (2, 1), (3, 2), (7, 3), (40, 4), (150, 5)])
+def test_hessenberg_eigenvalues_match_lapack(L, n, seed):
+    # the host step of the D-N spectrum: the Francis QR iteration on an upper
+    # Hessenberg matrix against LAPACK's general eigenvalue routine
+    import numpy as np
+    from paper_2110_10749_amd import binding as B
+    rng = np.random.default_rng(seed)
+    H = np.triu(rng.normal(size=(n, n)), -1)
+    got = np.array(B.hessenberg_eigenvalues(H))
+    ref = np.linalg.eigvals(H)
+    assert _match(got, ref) < 1e-10 * max(1.0, np.abs(H).sum())
+
+
+def test_hessenberg_eigenvalues_of_arnoldi_like_matrices(L):
+    # the Hessenberg matrix of Arnoldi on a matrix with clustered real
+    # eigenvalues (multiplets, as the D-N map has on a sphere) and a complex pair
+    import numpy as np
+    from paper_2110_10749_amd import binding as B
+    rng = np.random.default_rng(7)
+    lam = np.concatenate([np.full(3, -1 / 3) + 1e-6 * rng.normal(size=3),
+                          np.full(5, -0.104) + 1e-6 * rng.normal(size=5), rng.uniform(-0.05, 0.0, 60)])
+    n = lam.size + 2
+    D = np.zeros((n, n))
+    D[np.arange(lam.size), np.arange(lam.size)] = lam
+    D[-2:, -2:] = [[0.2, 0.3], [-0.3, 0.2]]
+    Q, _ = np.linalg.qr(rng.normal(size=(n, n)))
+    A = Q @ D @ Q.T
+    m = 50
+    V = np.zeros((n, m + 1))
+    Hm = np.zeros((m + 1, m))
+    v = rng.normal(size=n)
+    V[:, 0] = v / np.linalg.norm(v)
+    for k in range(m):
+        w = A @ V[:, k]
+        for _ in range(2):
+            h = V[:, :k + 1].T @ w
+            w -= V[:, :k + 1] @ h
+            Hm[:k + 1, k] += h
+        Hm[k + 1, k] = np.linalg.norm(w)
+        V[:, k + 1] = w / Hm[k + 1, k]
+    got = np.array(B.hessenberg_eigenvalues(Hm[:m, :m]))
+    assert _match(got, np.linalg.eigvals(Hm[:m, :m])) < 1e-12
+
+
+def test_hessenberg_eigenvalues_rejects_bad_arguments(L):
+    from paper_2110_10749_amd import binding as B
+    assert L.sdbie_hessenberg_eigenvalues(0, None, None, None) == B.ERR_ARG

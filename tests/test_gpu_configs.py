@@ -14,15 +14,15 @@
   the mixed solve over h = 1/16, 1/32, 1/64 on the nested node sets (the nodes
   at h are the nodes at h/2 on every second grid line).
 * The gradient of drag on the perturbed sphere with respect to log K, alpha
-  and 20 seeded node-coordinate directions against central differences of the
-  FP64 forward solve (step 1e-6, tight tolerances): at h = 1/32 always, at
-  h = 1/64 (the configuration's size, about 6.5 minutes) with SDBIE_LONG_TESTS=1.
+  and 20 seeded node-coordinate directions, through the autograd.Function
+  (drag().backward()), against central differences of the FP64 forward solve
+  (step 1e-6, tight tolerances), at h = 1/32 and at the configuration's size
+  h = 1/64 (N = 71002).
 * The large perturbed sphere (degree <= 8, h = 1/128, N = 351866), K = 1e-3,
   alpha = 1: sampled rows, and local Darcy and Stokes solves in both
-  precisions.
+  precisions with the oracle's residual of each on sampled rows.
 """
 import math
-import os
 import time
 
 import numpy as np
@@ -176,45 +176,77 @@ def test_mixed_solve_and_self_convergence(sd, kind):
     assert dp2 < 1e-3 and du2 < 1e-3 and dD2 < 1e-3
 
 
-LONG = os.environ.get("SDBIE_LONG_TESTS") == "1"
+# The drag gradient through the autograd.Function (forward ddm_solve, backward
+# ddm_adjoint from the checkpointed p and u), one forward and one backward per
+# surface, kept for the tests below; each test then checks a part of it against
+# central differences of the FP64 forward solve (about a minute per part at
+# h = 1/64, so that no single test runs for minutes).
+_ADJ = {}
 
 
-@pytest.mark.parametrize("inv_h", [32, pytest.param(64, marks=pytest.mark.skipif(
-    not LONG, reason="42 tight FP64 solves at N = 71002 take about 5 minutes; set SDBIE_LONG_TESTS=1"))])
-def test_adjoint_perturbed_central_differences(sd, inv_h):
+@pytest.fixture(scope="module")
+def adjoint_cache():
+    yield _ADJ
+    _ADJ.clear()
+
+
+def adjoint_case(sd, cache, inv_h):
+    if inv_h in cache:
+        return cache[inv_h]
     S = make_surface("perturbed", 1.0 / inv_h)
     delta = 3.0 / inv_h
     K, alpha = 1e-2, 1.0
     U = fields.unit_vector(41)
     e = fields.unit_vector(42)
-    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), delta)
+    x = dev(S.x).requires_grad_(True)
+    logK = torch.tensor(math.log(K), dtype=torch.float64, device="cuda", requires_grad=True)
+    a = torch.tensor(alpha, dtype=torch.float64, device="cuda", requires_grad=True)
+    t0 = time.perf_counter()
+    D = sd.drag(x, logK, a, dev(S.n), dev(S.w), delta, 1.0, U, None, TIGHT)
+    J = (D * torch.tensor(e, dtype=torch.float64, device="cuda")).sum()
+    J.backward()
+    print(f"h=1/{inv_h} N={S.N}: drag {D.tolist()} forward+backward {time.perf_counter() - t0:.1f} s", flush=True)
+    cache[inv_h] = dict(S=S, delta=delta, K=K, alpha=alpha, U=U, e=e, gx=host(x.grad),
+                        gK=float(logK.grad), ga=float(a.grad))
+    return cache[inv_h]
 
-    def J(x=None, K=K, alpha=alpha):
-        pl = plan if x is None else sd.Plan(dev(x), dev(S.n), dev(S.w), delta)
-        _, _, D, info = sd.ddm_solve(pl, 1.0, K, alpha, U, None, opts=TIGHT)
-        assert info["converged"]
-        if x is not None:
-            pl.close()
-        return float(np.dot(e, D))
 
-    p, u, D, info = sd.ddm_solve(plan, 1.0, K, alpha, U, None, opts=TIGHT)
-    gx, gK, ga, ainfo = sd.ddm_adjoint(plan, 1.0, K, alpha, U, p, u, e, None, opts=TIGHT)
-    assert ainfo["converged"]
-    gx = host(gx)
+def fd_drag(sd, c, x=None, K=None, alpha=None):
+    S = c["S"]
+    pl = sd.Plan(dev(S.x if x is None else x), dev(S.n), dev(S.w), c["delta"])
+    _, _, D, info = sd.ddm_solve(pl, 1.0, c["K"] if K is None else K, c["alpha"] if alpha is None else alpha,
+                                 c["U"], None, opts=TIGHT)
+    pl.close()
+    assert info["converged"]
+    return float(np.dot(c["e"], D))
+
+
+@pytest.mark.parametrize("inv_h", [32, 64])
+def test_adjoint_parameters_central_differences(sd, adjoint_cache, inv_h):
+    c = adjoint_case(sd, adjoint_cache, inv_h)
     hs = 1e-6
-    fdK = (J(K=K * math.exp(hs)) - J(K=K * math.exp(-hs))) / (2 * hs)
-    fda = (J(alpha=alpha + hs) - J(alpha=alpha - hs)) / (2 * hs)
-    print("logK", gK, fdK, "alpha", ga, fda, flush=True)
-    assert abs(gK - fdK) < 1e-5 * abs(fdK)
-    assert abs(ga - fda) < 1e-5 * abs(fda)
+    K, alpha = c["K"], c["alpha"]
+    fdK = (fd_drag(sd, c, K=K * math.exp(hs)) - fd_drag(sd, c, K=K * math.exp(-hs))) / (2 * hs)
+    fda = (fd_drag(sd, c, alpha=alpha + hs) - fd_drag(sd, c, alpha=alpha - hs)) / (2 * hs)
+    print(f"h=1/{inv_h}: d/dlogK {c['gK']:.10f} fd {fdK:.10f}; d/dalpha {c['ga']:.10f} fd {fda:.10f}", flush=True)
+    assert abs(c["gK"] - fdK) < 1e-5 * abs(fdK)
+    assert abs(c["ga"] - fda) < 1e-5 * abs(fda)
+
+
+@pytest.mark.parametrize("group", range(4))
+@pytest.mark.parametrize("inv_h", [32, 64])
+def test_adjoint_positions_central_differences(sd, adjoint_cache, inv_h, group):
+    # 20 seeded random directions in the node coordinates, 5 per test
+    c = adjoint_case(sd, adjoint_cache, inv_h)
+    S, hs = c["S"], 1e-6
     worst = 0.0
-    for k in range(20):
+    for k in range(5 * group, 5 * group + 5):
         V = fields.random_vector(S.N, 300 + k)
-        fd = (J(S.x + hs * V) - J(S.x - hs * V)) / (2 * hs)
-        ad = float((gx * V).sum())
+        fd = (fd_drag(sd, c, x=S.x + hs * V) - fd_drag(sd, c, x=S.x - hs * V)) / (2 * hs)
+        ad = float((c["gx"] * V).sum())
         err = abs(ad - fd) / max(abs(fd), 1e-3)
         worst = max(worst, err)
-        print("direction", k, ad, fd, f"{err:.1e}", flush=True)
+        print(f"h=1/{inv_h} direction {k}: adjoint {ad:.10f} fd {fd:.10f} rel {err:.1e}", flush=True)
     assert worst < 1e-4
 
 
@@ -241,5 +273,14 @@ def test_large_perturbed_sphere_h128(sd):
         print(prec, ip, iu, f"{time.perf_counter() - t0:.2f} s", flush=True)
         assert ip["converged"] and iu["converged"]
         res[prec] = (host(p), host(u))
+        # the oracle's residual of both local solves on 256 sampled rows (Darcy
+        # up to the constant the completion fixes); tolerance 1e-10 relative
+        rows = np.sort(np.random.default_rng(55).choice(S.N, size=256, replace=False))
+        geo = O.Geometry(S.x, S.n, S.w, delta)
+        r1, b1, r2, b2 = O.coupled_residual(geo, O.Params(1.0, K, alpha), U, host(p), host(u), rows, v=host(v))
+        e1 = float(np.sqrt(np.mean((r1 - r1.mean()) ** 2) / np.mean(b1 ** 2)))
+        e2 = float(np.sqrt(np.mean(r2 ** 2) / np.mean(b2 ** 2)))
+        print(f"{prec}: oracle residual on 256 rows: Darcy {e1:.2e} Stokes {e2:.2e}", flush=True)
+        assert e1 < 1e-8 and e2 < 1e-8
     assert rel(res["mixed"][0], res["fp64"][0]) < 1e-8
     assert rel(res["mixed"][1], res["fp64"][1]) < 1e-8

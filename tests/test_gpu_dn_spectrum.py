@@ -13,13 +13,27 @@ condition of eqs. CA16-CA17 (which give eq. CA31's (n+1)/(n(n+2)(2n-1))).
 The GPU map, applied to the zonal harmonics P_n(z), n = 1..8, converges to it
 at fifth order in h (delta = 3h): relative errors at h = 1/64 below 3e-4 and
 a factor above 16 between h = 1/32 and h = 1/64; both precisions.
+
+The eigenvalues of the relaxed iteration matrix A~ = (1 - theta) I + theta
+T_lin (eq. (A_mat), section "Discrete iteration operator"), as in the paper's
+figure of them (h = 1/16, N = 4302; kappa = 1 with theta = 0.5, 0.75; kappa =
+1e-2, 1e-4 with theta = c kappa, c = 0.5, 0.75, 0.9): the GPU's Arnoldi on
+T_lin (ddm_dn_spectrum, 240 steps, local solves to 1e-13) gives Ritz values
+whose leading 48 (the complete multiplets n = 1..6) match the eigenvalues of
+the oracle's dense A~ (tests/golden/oracle_spectrum_h16.json, written by
+tests/golden/make_oracle_spectrum.py) to 1e-8 of their spread, and each
+multiplet of 2n + 1 lies at the closed-form lambda_n within the
+discretisation error of h = 1/16.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
 from scipy.special import eval_legendre
 
-from workloads import surfaces
+from workloads import fields, surfaces
 
 pytestmark = pytest.mark.gpu
 
@@ -72,3 +86,52 @@ def test_dn_map_spectrum_sphere(sd, prec):
         assert b[n][1] < 1e-5  # P_n is an eigenfunction
         if n >= 2:
             assert ea / eb > 16.0  # fifth order in h
+
+
+SPEC = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_spectrum_h16.json")
+# discretisation error of lambda_n at h = 1/16 (the Rayleigh quotients of the oracle pins: 6.5e-5 .. 1e-2)
+DISC_H16 = {1: 2e-4, 2: 2e-3, 3: 8e-3, 4: 2e-2, 5: 4e-2, 6: 8e-2}
+
+
+@pytest.fixture(scope="module")
+def sphere16(sd):
+    S = surfaces.sphere(1.0 / 16)
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / 16, max_restart=240)
+    yield S, plan
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("K", [1.0, 1e-2, 1e-4])
+def test_iteration_matrix_eigenvalues_h16(sd, sphere16, K, prec):
+    S, plan = sphere16
+    with open(SPEC) as f:
+        spec = json.load(f)
+    v0 = fields.random_scalar(S.N, 90)
+    lam, info = sd.ddm_dn_spectrum(plan, 1.0, K, 0.0, dev(v0), 240, 60, opts=dict(prec=prec, tol_gmres=1e-13))
+    lam = np.array(lam)
+    print(f"K={K:g} {prec}: {info['ddm_iters']} Arnoldi steps, {info['gmres_iters']} local GMRES iterations; "
+          f"leading Ritz values {np.round(lam[:4].real, 8)}", flush=True)
+    assert info["converged"] and info["ddm_iters"] == 240
+    assert np.max(np.abs(lam[:48].imag)) < 1e-8 * np.max(np.abs(lam))
+    # multiplets of the degree-n harmonics at the closed-form lambda_n
+    start = 0
+    for n in range(1, 7):
+        ex = closed_form(n, K)
+        block = lam[start:start + 2 * n + 1].real
+        print(f"  n={n}: {2 * n + 1} Ritz values in [{block.min():.8e}, {block.max():.8e}], closed form {ex:.8e}",
+              flush=True)
+        assert np.all(np.abs(block - ex) < DISC_H16[n] * abs(ex))
+        start += 2 * n + 1
+    # the eigenvalues of A~ for the figure's relaxation parameters, against the oracle's dense A~
+    cfgs = [c for c in spec["configs"] if c["K"] == K]
+    assert len(cfgs) == (2 if K == 1.0 else 3)
+    for c in cfgs:
+        theta = c["theta"]
+        ref = np.array(c["re"]) + 1j * np.array(c["im"])
+        got = (1.0 - theta) + theta * lam
+        spread = np.max(np.abs(ref - (1.0 - theta)))
+        err = np.max(np.abs(got[:48] - ref[:48])) / spread
+        print(f"  theta={theta:g}: A~ eigenvalues {np.round(got[:3].real, 6)} ... vs oracle {err:.1e} "
+              f"(50th: {got[49].real:.8f} vs {ref[49].real:.8f})", flush=True)
+        assert err < 1e-8

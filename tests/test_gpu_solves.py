@@ -247,10 +247,12 @@ def test_large_slip_with_long_restart(sd, s16):
     K, alpha = 1e-2, 10.0
     pb, ub, Db = O.coupled_dense_solve(geo, O.Params(1.0, K, alpha), E)
     plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), geo.delta, max_restart=600)
-    for prec in ("fp64", "mixed"):
+    # the mixed schemes: relaxed GMRES (default) and iterative refinement of
+    # every local solve, whose convergence a double-pair residual decides
+    for prec, mode in (("fp64", "relaxed"), ("mixed", "relaxed"), ("mixed", "refine")):
         p, u, D, info = sd.ddm_solve(plan, 1.0, K, alpha, E, None,
-                                     opts=dict(prec=prec, restart=600, maxit_gmres=3000))
-        print(prec, info, rel(host(u), ub), rel(host(p), pb), rel(D, Db), flush=True)
+                                     opts=dict(prec=prec, mixed_mode=mode, restart=600, maxit_gmres=3000))
+        print(prec, mode, info, rel(host(u), ub), rel(host(p), pb), rel(D, Db), flush=True)
         assert info["converged"]
         assert rel(host(u), ub) < 1e-6 and rel(host(p), pb) < 1e-6 and rel(D, Db) < 1e-7
 
@@ -291,3 +293,28 @@ def test_biem_accuracy_problems_converge_at_fifth_order(sd):
     print("darcy", ep, "stokes", eu, flush=True)
     assert ep[1] < 1e-5 and eu[1] < 1e-5
     assert ep[1] / ep[2] > 20.0 and eu[1] / eu[2] > 20.0
+
+
+def test_translated_body_float_pairs(sd):
+    # the float pair coordinates are taken relative to the body's bounding-box
+    # centre: a sphere moved to (100, 0, 0) gives the same float-pair layer sums
+    # (against the oracle) and the same mixed solve as the sphere at the origin
+    S = surfaces.sphere(1.0 / 32)
+    delta = 3.0 / 32
+    shift = np.array([[100.0], [0.0], [0.0]])
+    q = fields.random_vector(S.N, 71)
+    out = {}
+    for name, x in (("origin", S.x), ("moved", S.x + shift)):
+        plan = sd.Plan(dev(x), dev(S.n), dev(S.w), delta)
+        geo = O.Geometry(x, S.n, S.w, delta)
+        rows = np.arange(0, S.N, 97)
+        g = host(sd.stokes_layer_apply(plan, 1.0, "dl_sub", dev(q), prec="mixed"))[:, rows]
+        r = O.stokes_apply(geo, 1.0, O.SDLS, q, rows)
+        err = rel(g, r)
+        p, u, D, info = sd.ddm_solve(plan, 1.0, 1e-2, 1.0, E, None, opts=dict(prec="mixed"))
+        print(name, f"float stresslet vs oracle {err:.1e}", D, info, flush=True)
+        assert err < 3e-6 and info["converged"]
+        out[name] = (host(u), D, info["applies_mixed"])
+        plan.close()
+    assert rel(out["moved"][1], out["origin"][1]) < 1e-9
+    assert rel(out["moved"][0], out["origin"][0]) < 1e-7

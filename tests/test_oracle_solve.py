@@ -234,3 +234,62 @@ def test_lagged_slip_reaches_same_fixed_point(small):
     b = O.ddm_solve(ops, prm, U, None, O.Opts(theta=0.75, slip="implicit", tol_gmres=1e-13, tol_ddm=1e-12))
     assert np.max(np.abs(a[1] - b[1])) < 1e-8
     assert np.max(np.abs(a[2] - b[2])) < 1e-8
+
+
+def test_coupled_residual_rows(small):
+    # the residual of the two fixed-point equations at sampled rows, as the
+    # GPU solutions at large N are checked: zero at the dense brute-force
+    # fixed point (the Darcy rows up to the constant that the completion
+    # fixes, minus the weighted mean of the completed pressure), and for any
+    # other (pt, u) the rows of the dense coupled system M z - b
+    g, ops = small
+    U = np.array([0.3, -0.5, 0.8])
+    prm = O.Params(mu=1.0, K=1e-2, alpha=1.0)
+    pb, ub, Db, pt = O.coupled_dense_solve(g, prm, U, return_pt=True)
+    rows = np.arange(3, g.N, 7)
+    r1, b1, r2, b2 = O.coupled_residual(g, prm, U, pb, ub, rows)
+    mean_pt = (g.w @ pt) / g.area
+    assert np.max(np.abs(r1 + mean_pt)) < 1e-11 * np.max(np.abs(b1))
+    assert np.max(np.abs(r2)) < 1e-11
+    rng = np.random.default_rng(5)
+    pt2 = pt + 0.1 * rng.normal(size=g.N)
+    u2 = ub + 0.1 * rng.normal(size=ub.shape)
+    M, V, SL, Pi, Ptau, Nrm = O._coupled_blocks(g, prm)
+    b = np.zeros(4 * g.N)
+    b[g.N:] = np.repeat(U, g.N)
+    res = M @ np.concatenate([pt2, u2.reshape(-1)]) - b
+    r1, b1, r2, b2 = O.coupled_residual(g, prm, U, Pi @ pt2, u2, rows)
+    assert np.allclose(r1, res[:g.N][rows] - (g.w @ pt2) / g.area, rtol=0, atol=1e-10)
+    assert np.allclose(r2, res[g.N:].reshape(3, g.N)[:, rows], rtol=0, atol=1e-10)
+    # the right-hand sides at the rows: (mu/K) S_L[u.n] and U - V[-p n]
+    v2 = (g.n * u2).sum(axis=0)
+    assert np.allclose(b1, (prm.mu / prm.K) * (SL @ v2)[rows], rtol=0, atol=1e-10)
+    pn = ((Pi @ pt2)[None, :] * g.n).reshape(-1)
+    assert np.allclose(b2, (np.repeat(U, g.N) + V @ pn).reshape(3, g.N)[:, rows], rtol=0, atol=1e-10)
+
+
+def test_dn_iteration_matrix_eigenvalues():
+    # eq. (A_mat): the leading eigenvalues of the relaxed D-N iteration matrix
+    # come in multiplets of the degree-n harmonics, 2n + 1 each, at
+    # (1 - theta) + theta lambda_n with the free-slip lambda_n of the closed
+    # form (h = 1/12 here: discretisation errors ~4e-4, 4e-3, 2e-2 for n = 1..3);
+    # at K = 1, theta = 1/2 the largest is the contraction factor 1/3 that the
+    # relaxed D-N loop shows (test_relaxation_contraction_factor)
+    S = surfaces.sphere(1.0 / 12)
+    g = O.Geometry(S.x, S.n, S.w, 3.0 / 12)
+    K = 1.0
+    lam_T = {}
+    for theta in (0.5, 0.75):
+        e = O.dn_iteration_eigenvalues(g, 1.0, K, theta, k=15)
+        assert np.max(np.abs(e.imag)) < 1e-8
+        lam_T[theta] = (e.real - (1.0 - theta)) / theta
+    # theta enters eq. (A_mat) affinely: the same lambda(T) from both
+    assert np.allclose(lam_T[0.5], lam_T[0.75], rtol=0, atol=1e-10)
+    lam = lam_T[0.5]
+    start = 0
+    for n, tol in ((1, 1e-3), (2, 1e-2), (3, 5e-2)):
+        free = -(1.0 / K) * (n + 1) * (2 * n + 1) / (2 * n * (n + 2) * (2 * n * n + 1))
+        block = lam[start:start + 2 * n + 1]
+        assert np.all(np.abs(block - free) < tol * abs(free)), (n, block, free)
+        start += 2 * n + 1
+    assert abs((1 - 0.5) + 0.5 * lam[0] - 1.0 / 3.0) < 1e-3
