@@ -172,6 +172,23 @@ int laplace_layer_apply(sdbie_plan plan, sdbie_layer layer, const double* dens, 
 int stokes_layer_apply(sdbie_plan plan, double mu, sdbie_layer layer, const double* dens,
                        double* out, sdbie_precision prec, void* stream);
 
+/* Allocation-free Stokes layer sum, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation): the same sums as stokes_layer_apply (same kernels) for
+ * a surface given directly, staged on every call into a fixed device array
+ * of the library (24 MiB per device the library runs on, held until the
+ * process ends) instead of a plan's workspace.  No device memory is
+ * allocated or freed.  Surfaces of 1 <= s->n <= SDBIE_NOALLOC_MAX_NODES
+ * nodes; larger ones return SDBIE_ERR_ARG (use a plan).  dens, out: device
+ * [3][n] in the caller's node order (out must not alias dens).  Staging
+ * synchronises `stream` (it reads back the finiteness check and the weight
+ * sum).  The array is shared by every call on a device and keeps the last
+ * call's contents: calls that overlap in time on one device race.  Errors as
+ * for sdbie_plan_create and stokes_layer_apply. */
+#define SDBIE_NOALLOC_MAX_NODES 32768
+int stokes_layer_apply_noalloc(const sdbie_surface* s, double mu, sdbie_layer layer, const double* dens,
+                               double* out, sdbie_precision prec, void* stream);
+
 /* Darcy problem, eq. (Darcy_final): given v = u.n on the nodes (device [n]),
  * solve (1/2 - H) p = b_D with b_D = -L dp/dn, dp/dn = -(mu/K) v, as
  * (A_D + w^T p/|S|) p = -S_L[dp/dn] by GMRES (the rank-one term fixes the

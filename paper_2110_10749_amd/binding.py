@@ -89,6 +89,8 @@ def lib():
         L.laplace_layer_apply.restype = i32
         L.stokes_layer_apply.argtypes = [vp, d, i32, vp, vp, i32, vp]
         L.stokes_layer_apply.restype = i32
+        L.stokes_layer_apply_noalloc.argtypes = [ctypes.POINTER(Surface), d, i32, vp, vp, i32, vp]
+        L.stokes_layer_apply_noalloc.restype = i32
         L.darcy_solve.argtypes = [vp, ctypes.POINTER(Params), vp, vp, ctypes.POINTER(Opts), ctypes.POINTER(Info), vp]
         L.darcy_solve.restype = i32
         L.stokes_solve.argtypes = [vp, ctypes.POINTER(Params), ctypes.POINTER(d), vp, vp, vp,
@@ -239,6 +241,24 @@ def stokes_layer_apply(plan: Plan, mu: float, layer, dens, out=None, prec="fp64"
     out = torch.empty_like(dens) if out is None else _dev(out, (3, plan.n), "out")
     _check(lib().stokes_layer_apply(plan.handle, float(mu), _LAYER[layer], _ptr(dens), _ptr(out), _PREC[prec],
                                     _stream(plan.device)))
+    return out
+
+
+NOALLOC_MAX_NODES = 32768  # SDBIE_NOALLOC_MAX_NODES
+
+
+def stokes_layer_apply_noalloc(x, nrm, w, delta: float, mu: float, layer, dens, out=None, prec="fp64"):
+    """Stokes layer sum of a surface given directly (no plan, no device allocation in the
+    library: the surface is staged into its static device array on every call)."""
+    n = int(w.shape[0])
+    x = _dev(x, (3, n), "x")
+    nrm = _dev(nrm, (3, n), "nrm")
+    w = _dev(w, (n,), "w")
+    dens = _dev(dens, (3, n), "dens")
+    out = torch.empty_like(dens) if out is None else _dev(out, (3, n), "out")
+    surf = Surface(n, x.data_ptr(), nrm.data_ptr(), w.data_ptr(), float(delta))
+    _check(lib().stokes_layer_apply_noalloc(ctypes.byref(surf), float(mu), _LAYER[layer], _ptr(dens), _ptr(out),
+                                            _PREC[prec], _stream(x.device)))
     return out
 
 

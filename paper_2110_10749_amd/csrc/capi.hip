@@ -138,6 +138,27 @@ hipStream_t stream_of(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 bool is_zero(Ctx& c, const double* a, int64_t len) { return c.norm(a, len) == 0.0; }
 
+int layer_splits(int64_t n, int nsplit_cap) {
+    const int S = choose_splits(n);
+    return S < nsplit_cap ? S : nsplit_cap;
+}
+
+// layer applies only: the common part with at most nsplit_cap splits and three
+// components per slot, then one [3][n] vector for the gathered density
+Layout layer_layout(int64_t n, int nsplit_cap) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    layout_common(L, take, n, 1, layer_splits(n, nsplit_cap), 3);
+    L.vecs = take((size_t)3 * n * sizeof(double));
+    L.total = off;
+    return L;
+}
+
 void carve_common(Plan& P, const Layout& L, char* b) {
     P.x = reinterpret_cast<double*>(b + L.x);
     P.nrm = reinterpret_cast<double*>(b + L.nrm);
@@ -177,6 +198,17 @@ void carve_workspace(Plan& P, void* ws) {
     P.basis_out = reinterpret_cast<double*>(b + L.basis_out);
     P.image_out = reinterpret_cast<double*>(b + L.image_out);
     P.basis_rc = reinterpret_cast<double*>(b + L.basis_rc);
+}
+
+size_t layer_workspace_bytes(int64_t n, int nsplit_cap) { return layer_layout(n, nsplit_cap).total; }
+
+void carve_layer_workspace(Plan& P, void* ws, int nsplit_cap, double** in) {
+    const Layout L = layer_layout(P.n, nsplit_cap);
+    char* b = static_cast<char*>(ws);
+    carve_common(P, L, b);
+    P.nsplit = layer_splits(P.n, nsplit_cap);
+    P.max_comps = 3;
+    *in = reinterpret_cast<double*>(b + L.vecs);
 }
 
 void apply_laplace_layer(Plan& P, sdbie_layer layer, const double* dens, double* out, sdbie_precision prec,
@@ -308,6 +340,14 @@ int stokes_layer_apply(sdbie_plan plan, double mu, sdbie_layer layer, const doub
     return guarded([&]() -> int {
         Plan& P = plan_of(plan);
         apply_stokes_layer(P, mu, layer, dens, out, prec, stream_of(stream), P.vec(kVecIn));
+        return SDBIE_OK;
+    });
+}
+
+int stokes_layer_apply_noalloc(const sdbie_surface* s, double mu, sdbie_layer layer, const double* dens,
+                               double* out, sdbie_precision prec, void* stream) {
+    return guarded([&]() -> int {
+        stokes_layer_apply_static(s, mu, layer, dens, out, prec, stream_of(stream));
         return SDBIE_OK;
     });
 }

@@ -151,12 +151,22 @@ constexpr int kImageStride = 8;  // doubles per node of one image-basis slot: p,
 
 size_t workspace_bytes(int64_t n, int max_restart);
 void carve_workspace(Plan& P, void* ws);
+// layer applies only (no solver vectors), at most nsplit_cap source splits and
+// three components per partial slot: bytes, and the carve (which also sets
+// *in, a [3][n] buffer for the gathered density)
+size_t layer_workspace_bytes(int64_t n, int nsplit_cap);
+void carve_layer_workspace(Plan& P, void* ws, int nsplit_cap, double** in);
 // the layer sums of the C ABI on a staged plan; `in` receives the density in
 // staged order ([n] or [3][n])
 void apply_laplace_layer(Plan& P, sdbie_layer layer, const double* dens, double* out, sdbie_precision prec,
                          hipStream_t st, double* in);
 void apply_stokes_layer(Plan& P, double mu, sdbie_layer layer, const double* dens, double* out,
                         sdbie_precision prec, hipStream_t st, double* in);
+
+// allocation-free layer sum (noalloc.hip): stages s into the library's static
+// device array and applies the Stokes layer
+void stokes_layer_apply_static(const sdbie_surface* s, double mu, sdbie_layer layer, const double* dens,
+                               double* out, sdbie_precision prec, hipStream_t st);
 
 // kernels (pair_kernels.hip) ----------------------------------------------------
 void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t s);

@@ -155,3 +155,15 @@ def test_hessenberg_eigenvalues_of_arnoldi_like_matrices(L):
 def test_hessenberg_eigenvalues_rejects_bad_arguments(L):
     from paper_2110_10749_amd import binding as B
     assert L.sdbie_hessenberg_eigenvalues(0, None, None, None) == B.ERR_ARG
+
+
+def test_noalloc_entry_point_rejects_arguments_on_the_host(L):
+    # the allocation-free layer sum checks its arguments before any device work
+    from paper_2110_10749_amd import binding as B
+    assert L.stokes_layer_apply_noalloc(None, 1.0, 0, None, None, 0, None) == B.ERR_ARG
+    assert b"null surface" in L.sdbie_last_error()
+    big = B.Surface(B.NOALLOC_MAX_NODES + 1, 4096, 4096, 4096, 0.1)
+    assert L.stokes_layer_apply_noalloc(ctypes.byref(big), 1.0, 0, None, None, 0, None) == B.ERR_ARG
+    assert b"allocation-free" in L.sdbie_last_error()
+    bad = B.Surface(100, 4096, 4096, 4096, -1.0)
+    assert L.stokes_layer_apply_noalloc(ctypes.byref(bad), 1.0, 0, None, None, 0, None) == B.ERR_ARG
