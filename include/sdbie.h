@@ -147,9 +147,12 @@ void sdbie_default_opts(sdbie_opts* o);
 
 /* Bytes of device workspace a plan for n nodes (1 <= n <= 2^23) and GMRES
  * restart length up to max_restart (1..1000) needs (0 if the arguments are
- * invalid).  Roughly (120 max_restart + 1161 + 96 S) n bytes plus
- * (n/256)^2 * 2, with S the source splits of a pair pass (a multiple of 8
- * up to 64: 64 at n = 4096, 16 at n = 68166, 8 from n = 131072 on). */
+ * invalid).  Roughly (120 max_restart + 1185 + 96 S) n bytes plus
+ * (n/256)^2 * 3471, with S the source splits of a pair pass (a multiple of 8
+ * up to 64: 64 at n = 4096, 16 at n = 68166, 8 from n = 131072 on); the
+ * quadratic term is the tile masks and the partial sums of the symmetric far
+ * field (sdbie_plan_set_symmetric): 0.84 GB at n = 68166, 9.4 GB at n = 351866
+ * with max_restart = 50. */
 size_t sdbie_workspace_bytes(int64_t n, int max_restart);
 
 /* Stage a surface: spatial (Morton) ordering, double and float copies of the
@@ -163,6 +166,16 @@ int sdbie_plan_create(sdbie_plan* plan, const sdbie_surface* s, int max_restart,
                       void* ws, size_t ws_bytes, void* stream);
 int sdbie_plan_destroy(sdbie_plan plan);
 int64_t sdbie_plan_n(sdbie_plan plan);
+
+/* Target-source symmetric far field (section "Numerical Results", local
+ * problems: the paper's code evaluates each pair of nodes once for both
+ * directions).  on = 1: every later layer sum and solve on the plan (the
+ * transposed sums of ddm_adjoint excepted) evaluates each tile pair whose
+ * node pairs all lie beyond the smoothing cutoff once, adding its
+ * contributions to the targets of both tiles; near tile pairs stay one pass
+ * per direction.  Same sums up to rounding.  on = 0 (the default): every
+ * ordered pair in its own pass.  ERR_ARG for a null plan or on not 0/1. */
+int sdbie_plan_set_symmetric(sdbie_plan plan, int on);
 
 /* out = layer sum of `dens` (device, [n] for Laplace, [3][n] for Stokes, in
  * the caller's node order) at every node.  out must not alias dens.

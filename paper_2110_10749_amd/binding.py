@@ -85,6 +85,8 @@ def lib():
         L.sdbie_plan_destroy.restype = i32
         L.sdbie_plan_n.argtypes = [vp]
         L.sdbie_plan_n.restype = i64
+        L.sdbie_plan_set_symmetric.argtypes = [vp, i32]
+        L.sdbie_plan_set_symmetric.restype = i32
         L.laplace_layer_apply.argtypes = [vp, i32, vp, vp, i32, vp]
         L.laplace_layer_apply.restype = i32
         L.stokes_layer_apply.argtypes = [vp, d, i32, vp, vp, i32, vp]
@@ -215,6 +217,10 @@ class Plan:
     @property
     def handle(self):
         return self._h
+
+    def set_symmetric(self, on: bool = True) -> None:
+        """Evaluate the far tile pairs once for both directions (sdbie_plan_set_symmetric)."""
+        _check(lib().sdbie_plan_set_symmetric(self._h, 1 if on else 0))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

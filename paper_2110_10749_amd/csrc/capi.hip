@@ -26,8 +26,14 @@ int64_t next_pow2(int64_t n) {
 
 struct Layout {
     size_t x, nrm, w, wn, px, pn, pw, px32, boxes, uboxes, mask64, mask32, perm, keys, partial, rec, red, scal, vecs,
-        basis_in, basis_out, image_out, basis_rc, total;
+        basis_in, basis_out, image_out, basis_rc, sym_items[2], sym_blocks[2], sym_fwd_start[2], sym_rev_start[2],
+        sym_fwd, sym_rev, total;
 };
+
+// bounds of the symmetric far-field lists: at most T (T - 1) / 2 far tile
+// pairs, and at most pairs / kSymChunk + T blocks
+int64_t sym_max_pairs(int64_t nt) { return nt * (nt - 1) / 2; }
+int64_t sym_max_blocks(int64_t nt) { return sym_max_pairs(nt) / kSymChunk + nt; }
 
 // the node data, staging and pair-pass scratch every plan holds: nsplit
 // source splits with up to `comps` components per partial slot, m the
@@ -71,6 +77,15 @@ Layout layout(int64_t n, int m) {
     L.basis_out = take((size_t)(m + 1) * n * d);
     L.image_out = take((size_t)(m + 1) * kImageStride * n * d);
     L.basis_rc = take((size_t)(m + 1) * 3 * n * d);
+    const int64_t nt = (n + kTile - 1) / kTile;
+    for (int k = 0; k < 2; ++k) {
+        L.sym_items[k] = take((size_t)sym_max_pairs(nt) * 3 * sizeof(int32_t));
+        L.sym_blocks[k] = take((size_t)sym_max_blocks(nt) * 2 * sizeof(int32_t));
+        L.sym_fwd_start[k] = take((size_t)(nt + 1) * sizeof(int32_t));
+        L.sym_rev_start[k] = take((size_t)(nt + 1) * sizeof(int32_t));
+    }
+    L.sym_fwd = take((size_t)sym_max_blocks(nt) * 3 * kTile * d);
+    L.sym_rev = take((size_t)sym_max_pairs(nt) * 3 * kTile * d);  // double partials for the FP64 passes
     L.total = off;
     return L;
 }
@@ -198,6 +213,14 @@ void carve_workspace(Plan& P, void* ws) {
     P.basis_out = reinterpret_cast<double*>(b + L.basis_out);
     P.image_out = reinterpret_cast<double*>(b + L.image_out);
     P.basis_rc = reinterpret_cast<double*>(b + L.basis_rc);
+    for (int k = 0; k < 2; ++k) {
+        P.sym_items[k] = reinterpret_cast<int32_t*>(b + L.sym_items[k]);
+        P.sym_blocks[k] = reinterpret_cast<int32_t*>(b + L.sym_blocks[k]);
+        P.sym_fwd_start[k] = reinterpret_cast<int32_t*>(b + L.sym_fwd_start[k]);
+        P.sym_rev_start[k] = reinterpret_cast<int32_t*>(b + L.sym_rev_start[k]);
+    }
+    P.sym_fwd = reinterpret_cast<double*>(b + L.sym_fwd);
+    P.sym_rev = b + L.sym_rev;
 }
 
 size_t layer_workspace_bytes(int64_t n, int nsplit_cap) { return layer_layout(n, nsplit_cap).total; }
@@ -325,6 +348,15 @@ int sdbie_plan_destroy(sdbie_plan plan) {
 }
 
 int64_t sdbie_plan_n(sdbie_plan plan) { return plan ? reinterpret_cast<Plan*>(plan)->n : -1; }
+
+int sdbie_plan_set_symmetric(sdbie_plan plan, int on) {
+    return guarded([&]() -> int {
+        Plan& P = plan_of(plan);
+        if (on != 0 && on != 1) fail(SDBIE_ERR_ARG, "on must be 0 or 1");
+        P.symmetric = on == 1;
+        return SDBIE_OK;
+    });
+}
 
 int laplace_layer_apply(sdbie_plan plan, sdbie_layer layer, const double* dens, double* out, sdbie_precision prec,
                         void* stream) {

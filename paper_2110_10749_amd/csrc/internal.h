@@ -49,6 +49,7 @@ constexpr int kRecBytes = 128;   // largest per-source record of a pair pass
 #define SDBIE_GROUP_BYTES_F64 128
 #endif
 constexpr int kMaxRestart = 1000; // largest GMRES restart length of a plan
+constexpr int kSymChunk = 8;      // far tile pairs per block of the symmetric far field
 #ifndef SDBIE_SPLIT_TARGET
 #define SDBIE_SPLIT_TARGET 4096      // far-field blocks a pass kernel aims for (the near-field blocks double them)
 #endif
@@ -140,6 +141,19 @@ struct Plan {
     double* host_pinned = nullptr;  // not used (host buffers are plain)
     // (target, source) pairs of real nodes in the near tile pairs (double, float masks)
     double near_pairs64 = 0.0, near_pairs32 = 0.0;
+    // target-source symmetric far field (used when `symmetric` is set): per
+    // precision (index 0 double, 1 float) the far tile pairs {a < b} numbered
+    // in column order (pair p owns a reverse slot), the work items (a, b, p) in
+    // row order cut into blocks of at most kSymChunk items, the first block of
+    // each target tile and the first pair of each source tile
+    bool symmetric = false;
+    int32_t* sym_items[2] = {};      // [npairs][3]
+    int32_t* sym_blocks[2] = {};     // [nblocks][2]: first item, item count
+    int32_t* sym_fwd_start[2] = {};  // [ntiles + 1]
+    int32_t* sym_rev_start[2] = {};  // [ntiles + 1]
+    int sym_nblocks[2] = {0, 0}, sym_npairs[2] = {0, 0};
+    double* sym_fwd = nullptr;       // [nblocks][C][kTile] forward partials of the target tile, C <= 3
+    void* sym_rev = nullptr;         // [npairs][C][kTile] reverse partials of the source tile (pass precision)
     // bookkeeping for info
     int64_t applies_fp64 = 0, applies_mixed = 0;
     double pairs = 0.0;

@@ -32,6 +32,7 @@
 // plain 1/r^p kernels are used.
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 #include "internal.h"
 #include "smoothing_coeffs.h"
@@ -1003,6 +1004,270 @@ __global__ void epilogue(int64_t n, int nslots, const double* __restrict__ parti
     }
 }
 
+// --------------------------------------------------------------------------
+// Target-source symmetric far field.  The pair kernels are even (single
+// layers) or odd (double layers) in D = x_i - x_j, so the two ordered pairs of
+// one unordered pair share the geometry (D, r, 1/r) and most of the kernel
+// algebra; the paper's CPU code halves its pair work this way.  Here each far
+// tile pair {a, b} (a < b, every pair beyond the cutoff) is evaluated once:
+// every lane of a block holds one target of tile a and, in turn, one source
+// of tile b.  Within a wave the sources move across the 16 lanes of each row
+// by DPP row rotations, so at every step each lane evaluates one pair, adds
+// the forward contribution to its own target and hands the reverse one back
+// to the source's lane through the inverse rotation.  A wave meets its 64
+// targets with a quarter of the 256 sources per phase (4 row rotations of 16
+// steps); the quarters' reverse accumulators pass between the waves in LDS.
+// Forward sums of the target tile go to one slot per block, reverse sums of
+// the source tile to one slot per tile pair; the symmetric epilogue adds them
+// (and the near-field slots) in a fixed order.
+// --------------------------------------------------------------------------
+
+// lane l of a 16-lane row reads lane (l - K) mod 16 of the same row (DPP
+// row_ror:K; K = 0 reads itself).  rot<K> and rot<16 - K> are inverse
+// permutations whichever way the hardware rotates, which is all the
+// symmetric pass relies on.  A rotation reads a valid lane everywhere, so the
+// bound control is set and no old value needs to be kept in the destination.
+template <int K>
+__device__ __forceinline__ float rot(float v) {
+    if constexpr (K == 0) {
+        return v;
+    } else {
+        return __builtin_bit_cast(
+            float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x120 + K, 0xf, 0xf, true));
+    }
+}
+template <int K>
+__device__ __forceinline__ double rot(double v) {
+    if constexpr (K == 0) {
+        return v;
+    } else {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x120 + K, 0xf, 0xf, true);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x120 + K, 0xf, 0xf, true);
+        return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+    }
+}
+
+// One step of the symmetric Laplace far field: the lane's target t against
+// the source of the lane K places back in its row (its record read through
+// rot<K>).  Forward (into acc, target t): c_dl w_s (q_s - SUB q_t)(D.n_s) / r^3
+// + c_sl w_s g_s / r; reverse (returned, for source s): the same kernels with
+// D -> -D and the roles swapped, (q_s - q_t)(D.n_t) / r^3 (SUB) or -q_t
+// (D.n_t) / r^3, plus c_sl w_t g_t / r.  Records as LaplaceOp's.
+template <typename T, bool DL, bool SL, bool SUB>
+struct SymLaplace {
+    using Op = LaplaceOp<T, DL, SL, SUB>;
+    static constexpr int C = 1, R = Op::R;
+    static constexpr int Q = Op::Q, NX = Op::NX, NY = Op::NY, NZ = Op::NZ, G = Op::G;
+    template <int K>
+    __device__ __forceinline__ static void step(const T (&tr)[R], const T (&sr)[R], T (&acc)[C], T (&racc)[C]) {
+        const T dx = tr[0] - rot<K>(sr[0]), dy = tr[1] - rot<K>(sr[1]), dz = tr[2] - rot<K>(sr[2]);
+        const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const T ir = rsq_pos(r2);
+        T f = T(0), rv = T(0);
+        if constexpr (DL) {
+            const T k2 = ir * ir * ir;
+            const T dns = fma(dx, rot<K>(sr[NX]), fma(dy, rot<K>(sr[NY]), dz * rot<K>(sr[NZ])));
+            const T dnt = fma(dx, tr[NX], fma(dy, tr[NY], dz * tr[NZ]));
+            const T qs = rot<K>(sr[Q]);
+            if constexpr (SUB) {
+                const T dq = (qs - tr[Q]) * k2;
+                f = dq * dns;
+                rv = dq * dnt;
+            } else {
+                f = qs * dns * k2;
+                rv = -tr[Q] * dnt * k2;
+            }
+        }
+        if constexpr (SL) {
+            f = fma(rot<K>(sr[G]), ir, f);
+            rv = fma(tr[G], ir, rv);
+        }
+        acc[0] += f;
+        racc[0] += rot<(16 - K) & 15>(rv);
+    }
+};
+
+// One step of the symmetric Stokes far field (records as StokesOp's: n and f
+// carry c w of their node, u does not).  With D' = -D and ud' = (u_t - SUB
+// u_s).D' the reverse terms are those of the forward ones with the target's
+// fields: the stresslet ud' (D'.n_t) D' / r^5 = ud' (D.n_t) D / r^5 and the
+// Stokeslet [f_t + D (D.f_t) / r^2] / r; with both, 1/r is factored out as in
+// StokesOp.  ud' = ud with the subtraction, -(u_t.D) without it.
+template <typename T, bool DL, bool SL, bool SUB, bool SLIP>
+struct SymStokes {
+    using Op = StokesOp<T, DL, SL, SUB, SLIP>;
+    static constexpr int C = 3, R = Op::R;
+    static constexpr int NX = Op::NX, NY = Op::NY, NZ = Op::NZ, UX = Op::UX, UY = Op::UY, UZ = Op::UZ;
+    static constexpr int FX = Op::FX, FY = Op::FY, FZ = Op::FZ;
+    template <int K>
+    __device__ __forceinline__ static void step(const T (&tr)[R], const T (&sr)[R], T (&acc)[C], T (&racc)[C]) {
+        const T dx = tr[0] - rot<K>(sr[0]), dy = tr[1] - rot<K>(sr[1]), dz = tr[2] - rot<K>(sr[2]);
+        const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
+        const T ir = rsq_pos(r2);
+        const T ir2 = ir * ir;
+        T ud = T(0), udr = T(0), dns = T(0), dnt = T(0);
+        if constexpr (DL) {
+            const T ux = rot<K>(sr[UX]) - (SUB ? tr[UX] : T(0));
+            const T uy = rot<K>(sr[UY]) - (SUB ? tr[UY] : T(0));
+            const T uz = rot<K>(sr[UZ]) - (SUB ? tr[UZ] : T(0));
+            ud = fma(ux, dx, fma(uy, dy, uz * dz));
+            udr = SUB ? ud : -fma(tr[UX], dx, fma(tr[UY], dy, tr[UZ] * dz));
+            dns = fma(dx, rot<K>(sr[NX]), fma(dy, rot<K>(sr[NY]), dz * rot<K>(sr[NZ])));
+            dnt = fma(dx, tr[NX], fma(dy, tr[NY], dz * tr[NZ]));
+        }
+        T rc[3];
+        if constexpr (SL) {
+            const T q = ir2 * ir;
+            const T fsx = rot<K>(sr[FX]), fsy = rot<K>(sr[FY]), fsz = rot<K>(sr[FZ]);
+            const T dfs = fma(dx, fsx, fma(dy, fsy, dz * fsz));
+            const T dft = fma(dx, tr[FX], fma(dy, tr[FY], dz * tr[FZ]));
+            const T ef = (DL ? fma(ud * dns, ir2, dfs) : dfs) * q;
+            const T er = (DL ? fma(udr * dnt, ir2, dft) : dft) * q;
+            acc[0] = fma(fsx, ir, fma(ef, dx, acc[0]));
+            acc[1] = fma(fsy, ir, fma(ef, dy, acc[1]));
+            acc[2] = fma(fsz, ir, fma(ef, dz, acc[2]));
+            rc[0] = fma(er, dx, tr[FX] * ir);
+            rc[1] = fma(er, dy, tr[FY] * ir);
+            rc[2] = fma(er, dz, tr[FZ] * ir);
+        } else {
+            const T k4 = ir * ir2 * ir2;
+            const T cf = ud * dns * k4, cr = udr * dnt * k4;
+            acc[0] = fma(cf, dx, acc[0]);
+            acc[1] = fma(cf, dy, acc[1]);
+            acc[2] = fma(cf, dz, acc[2]);
+            rc[0] = cr * dx;
+            rc[1] = cr * dy;
+            rc[2] = cr * dz;
+        }
+        racc[0] += rot<(16 - K) & 15>(rc[0]);
+        racc[1] += rot<(16 - K) & 15>(rc[1]);
+        racc[2] += rot<(16 - K) & 15>(rc[2]);
+    }
+};
+
+template <class Op> struct SymOf { using type = void; };
+template <typename T, bool DL, bool SL, bool SUB>
+struct SymOf<LaplaceOp<T, DL, SL, SUB>> { using type = SymLaplace<T, DL, SL, SUB>; };
+template <typename T, bool DL, bool SL, bool SUB, bool SLIP>
+struct SymOf<StokesOp<T, DL, SL, SUB, SLIP>> { using type = SymStokes<T, DL, SL, SUB, SLIP>; };
+
+// the 16 steps of one row rotation, K = 0 .. 15 (compile-time DPP controls)
+template <class Sym, typename T, int K>
+struct SymSteps {
+    __device__ __forceinline__ static void run(const T (&tr)[Sym::R], const T (&sr)[Sym::R], T (&acc)[Sym::C],
+                                               T (&racc)[Sym::C]) {
+        Sym::template step<K>(tr, sr, acc, racc);
+        SymSteps<Sym, T, K + 1>::run(tr, sr, acc, racc);
+    }
+};
+template <class Sym, typename T>
+struct SymSteps<Sym, T, 16> {
+    __device__ __forceinline__ static void run(const T (&)[Sym::R], const T (&)[Sym::R], T (&)[Sym::C],
+                                               T (&)[Sym::C]) {}
+};
+
+struct SymArgs {
+    int nblocks;
+    const int32_t* items;   // [npairs][3]: target tile a, source tile b, pair index p
+    const int32_t* blocks;  // [nblocks][2]: first item, item count
+    double* fwd;            // [nblocks][C][kTile]
+    void* rev;              // [npairs][C][kTile] of T
+};
+
+template <class Sym, typename T>
+__device__ __forceinline__ void sym_far_body(const KArgs& a, const SymArgs& sa, int blk) {
+    constexpr int R = Sym::R, C = Sym::C;
+    static_assert(kTile == kTPB && kTile == 256, "one target and one staged source per thread, four waves");
+    __shared__ T srec[kTile * R];
+    __shared__ T sracc[C * kTile];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int first = sa.blocks[2 * blk], cnt = sa.blocks[2 * blk + 1];
+    const int ta = sa.items[3 * first];
+    const T* rec = static_cast<const T*>(a.rec);
+    T tr[R];
+#pragma unroll
+    for (int f = 0; f < R; ++f) tr[f] = rec[((int64_t)ta * kTile + tid) * R + f];
+    double acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.0;
+    T* rev = static_cast<T*>(sa.rev);
+    for (int it = first; it < first + cnt; ++it) {
+        const int tb = sa.items[3 * it + 1], p = sa.items[3 * it + 2];
+        __syncthreads();  // the previous tile pair is done with the LDS
+#pragma unroll
+        for (int f = 0; f < R; ++f) srec[tid * R + f] = rec[((int64_t)tb * kTile + tid) * R + f];
+#pragma unroll
+        for (int c = 0; c < C; ++c) sracc[c * kTile + tid] = T(0);
+        __syncthreads();
+        T facc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) facc[c] = T(0);
+#pragma unroll 1
+        for (int ph = 0; ph < 4; ++ph) {
+            const int q = (wave + ph) & 3;  // the four waves take the four quarters of the sources
+#pragma unroll 1
+            for (int rr = 0; rr < 4; ++rr) {
+                // row r of the wave holds row (r + rr) mod 4 of the quarter
+                const int j = 64 * q + ((((lane >> 4) + rr) & 3) << 4) + (lane & 15);
+                T sr[R], racc[C];
+#pragma unroll
+                for (int f = 0; f < R; ++f) sr[f] = srec[j * R + f];
+#pragma unroll
+                for (int c = 0; c < C; ++c) racc[c] = sracc[c * kTile + j];
+                SymSteps<Sym, T, 0>::run(tr, sr, facc, racc);
+#pragma unroll
+                for (int c = 0; c < C; ++c) sracc[c * kTile + j] = racc[c];
+            }
+            __syncthreads();  // each quarter's reverse sums go to the wave that takes it next
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            acc[c] += (double)facc[c];
+            rev[((int64_t)p * C + c) * kTile + tid] = sracc[c * kTile + tid];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) sa.fwd[((int64_t)blk * C + c) * kTile + tid] = acc[c];
+}
+
+// symmetric far blocks first, then the near-field blocks of the pass
+template <class Op, class Sym, typename T>
+__global__ __launch_bounds__(kTPB) void sym_pass_pairs(KArgs a, SymArgs sa) {
+    if ((int)blockIdx.x < sa.nblocks) sym_far_body<Sym, T>(a, sa, blockIdx.x);
+    else near_body<Op, T>(a, (int)blockIdx.x - sa.nblocks);
+}
+
+// Sum of the symmetric pass per target, in a fixed order: the forward slots
+// of its tile's blocks, the reverse slots of its tile's pairs, the near-field
+// split slots; then the terms of epilogue().
+template <int C, typename RT>
+__global__ void sym_epilogue(int64_t n, const int32_t* __restrict__ fwd_start, const double* __restrict__ fwd,
+                             const int32_t* __restrict__ rev_start, const RT* __restrict__ rev, int nsplit,
+                             const double* __restrict__ partial, const double* __restrict__ tw, const double* base,
+                             double base_scale, const double* __restrict__ comp, double comp_scale,
+                             const double* __restrict__ nrm, double add0, double add1, double add2, double* out,
+                             const int32_t* __restrict__ perm) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t t = i / kTile, j = i % kTile;
+    const double cs = comp ? comp_scale * comp[0] : 0.0;
+    const int64_t o = perm ? (int64_t)perm[i] : i;
+    const int b0 = fwd_start[t], b1 = fwd_start[t + 1], p0 = rev_start[t], p1 = rev_start[t + 1];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        double v = 0.0;
+        for (int b = b0; b < b1; ++b) v += fwd[((int64_t)b * C + c) * kTile + j];
+        for (int p = p0; p < p1; ++p) v += (double)rev[((int64_t)p * C + c) * kTile + j];
+        for (int s = 0; s < nsplit; ++s) v += partial[((int64_t)(nsplit + s) * C + c) * n + i];
+        if (tw) v *= tw[i];
+        if (base) v += base_scale * base[c * n + i];
+        if (comp) v += cs * (C == 3 ? nrm[c * n + i] : 1.0);
+        v += (c == 0 ? add0 : (c == 1 ? add1 : add2));
+        out[c * n + o] = v;
+    }
+}
+
 KArgs make_args(const Plan& P, const PassDesc& d, int nsplit, double cut) {
     KArgs a;
     a.n = P.n;
@@ -1041,8 +1306,10 @@ struct family_is_gradient<GradOp<SWAP>> { static constexpr bool value = true; };
 // pack and pair kernels of one pass, each timed on its own when kernel timing
 // is on (pairs: all N^2 for a pass kernel; with separate far and near
 // launches, the real-node pairs of the far / near tile pairs)
+// Returns true when the far field ran target-source symmetric (the sums then
+// need sym_epilogue).
 template <class Op, typename T>
-void launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int family, int code, bool mixed) {
+bool launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int family, int code, bool mixed) {
     static_assert(Op::R * sizeof(T) <= kRecBytes, "record larger than its workspace slot");
     if (Op::C > P.max_comps) throw Error(SDBIE_ERR_ARG, "this workspace holds no partial slots for that pass");
     const double all = (double)P.n * (double)P.n;
@@ -1051,6 +1318,23 @@ void launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int fami
         ProfScope prof(prof_variant(family, mixed, code, 2), 0.0, st);
         hipLaunchKernelGGL((pack_sources<Op, T>), dim3((unsigned)(a.npad / 256)), dim3(256), 0, st, a);
         SDBIE_LAUNCHED();
+    }
+    using Sym = typename SymOf<Op>::type;
+    if constexpr (!std::is_same<Sym, void>::value) {
+        const int k = mixed ? 1 : 0;
+        if (P.symmetric && P.sym_items[k] && P.sym_nblocks[k] > 0 && !a.dl_tgt) {
+            SymArgs sa;
+            sa.nblocks = P.sym_nblocks[k];
+            sa.items = P.sym_items[k];
+            sa.blocks = P.sym_blocks[k];
+            sa.fwd = P.sym_fwd;
+            sa.rev = P.sym_rev;
+            ProfScope prof(prof_variant(family, mixed, code, 4), all, st);
+            hipLaunchKernelGGL((sym_pass_pairs<Op, Sym, T>), dim3((unsigned)(sa.nblocks + a.ntiles * a.nsplit)),
+                               dim3(kTPB), 0, st, a, sa);
+            SDBIE_LAUNCHED();
+            return true;
+        }
     }
     const dim3 grid((unsigned)((int64_t)a.ntiles * a.nsplit));
     if constexpr (SDBIE_ONE_LAUNCH) {
@@ -1063,7 +1347,7 @@ void launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int fami
         else
             hipLaunchKernelGGL((pass_pairs<Op, T>), dim3(2 * grid.x), dim3(kTPB), 0, st, a);
         SDBIE_LAUNCHED();
-        return;
+        return false;
     }
     {
         ProfScope prof(prof_variant(family, mixed, code, 0), all - near, st);
@@ -1078,6 +1362,38 @@ void launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int fami
         hipLaunchKernelGGL((near_pairs<Op, T>), grid, dim3(kTPB), 0, st, a);
         SDBIE_LAUNCHED();
     }
+    return false;
+}
+
+// The epilogue of a pass: split (and, after a symmetric far field, block and
+// tile-pair) partials summed per target, then the pass's extra terms.
+template <int C>
+void launch_epilogue(const Plan& P, const PassDesc& d, int S, bool sym, hipStream_t st) {
+    const unsigned eb = (unsigned)((P.n + 255) / 256);
+    const double* add = d.add_const;
+    const double a0 = add ? add[0] : 0.0, a1 = add && C > 1 ? add[1] : 0.0, a2 = add && C > 2 ? add[2] : 0.0;
+    const double* tw = d.target_weight ? (const double*)P.w : nullptr;
+    const int32_t* perm = d.scatter ? (const int32_t*)P.perm : nullptr;
+    if (sym) {
+        const int k = d.mixed ? 1 : 0;
+        if (d.mixed)
+            hipLaunchKernelGGL((sym_epilogue<C, float>), dim3(eb), dim3(256), 0, st, P.n,
+                               (const int32_t*)P.sym_fwd_start[k], (const double*)P.sym_fwd,
+                               (const int32_t*)P.sym_rev_start[k], (const float*)P.sym_rev, S,
+                               (const double*)P.partial, tw, d.base, d.base_scale, d.comp, d.comp_scale,
+                               (const double*)P.nrm, a0, a1, a2, d.out, perm);
+        else
+            hipLaunchKernelGGL((sym_epilogue<C, double>), dim3(eb), dim3(256), 0, st, P.n,
+                               (const int32_t*)P.sym_fwd_start[k], (const double*)P.sym_fwd,
+                               (const int32_t*)P.sym_rev_start[k], (const double*)P.sym_rev, S,
+                               (const double*)P.partial, tw, d.base, d.base_scale, d.comp, d.comp_scale,
+                               (const double*)P.nrm, a0, a1, a2, d.out, perm);
+    } else {
+        hipLaunchKernelGGL((epilogue<C>), dim3(eb), dim3(256), 0, st, P.n, 2 * S, (const double*)P.partial, tw,
+                           d.base, d.base_scale, d.comp, d.comp_scale, (const double*)P.nrm, a0, a1, a2, d.out,
+                           perm);
+    }
+    SDBIE_LAUNCHED();
 }
 
 }  // namespace
@@ -1115,13 +1431,14 @@ void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
     const double cut = d.mixed ? (double)SDBIE_RHO_CUT_STOKES_F32 : SDBIE_RHO_CUT_STOKES_F64;
     const KArgs a = make_args(P, d, S, cut);
     const int code = (d.dl ? 1 : 0) | (d.sl ? 2 : 0) | (d.sub ? 4 : 0);
+    bool sym = false;
     if (d.target_normal) {
         if (!d.dl || d.sl || d.sub) throw Error(SDBIE_ERR_ARG, "transposed Laplace pass takes a double layer only");
         if (d.mixed) launch_pair_kernels<LaplaceTNOp<float>, float>(P, a, st, 0, 16 | 1, true);
         else launch_pair_kernels<LaplaceTNOp<double>, double>(P, a, st, 0, 16 | 1, false);
     } else {
         const int pc = d.sl && !d.dl ? 2 : code;
-#define SDBIE_LAP(T, DL, SL, SUB) launch_pair_kernels<LaplaceOp<T, DL, SL, SUB>, T>(P, a, st, 0, pc, d.mixed)
+#define SDBIE_LAP(T, DL, SL, SUB) sym = launch_pair_kernels<LaplaceOp<T, DL, SL, SUB>, T>(P, a, st, 0, pc, d.mixed)
         if (!d.mixed) {
             switch (code) {
                 case 1: SDBIE_LAP(double, true, false, false); break;
@@ -1143,13 +1460,7 @@ void launch_laplace_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
         }
 #undef SDBIE_LAP
     }
-    const double* add = d.add_const;
-    hipLaunchKernelGGL((epilogue<1>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P.n, 2 * S,
-                       (const double*)P.partial, d.target_weight ? (const double*)P.w : nullptr, d.base,
-                       d.base_scale, d.comp, d.comp_scale,
-                       (const double*)P.nrm, add ? add[0] : 0.0, 0.0, 0.0, d.out,
-                       d.scatter ? (const int32_t*)P.perm : nullptr);
-    SDBIE_LAUNCHED();
+    launch_epilogue<1>(P, d, S, sym, st);
     Plan& Pm = const_cast<Plan&>(P);
     (d.mixed ? Pm.applies_mixed : Pm.applies_fp64) += 1;
     Pm.pairs += (double)P.n * (double)P.n;
@@ -1179,13 +1490,14 @@ void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
         Pm.pairs += (double)P.n * (double)P.n;
         return;
     }
+    bool sym = false;
     if (d.target_normal) {
         if (!d.dl || d.sl || d.sub) throw Error(SDBIE_ERR_ARG, "transposed Stokes pass takes a double layer only");
         if (d.mixed) launch_pair_kernels<StokesTNOp<float>, float>(P, a, st, 1, 16 | 1, true);
         else launch_pair_kernels<StokesTNOp<double>, double>(P, a, st, 1, 16 | 1, false);
     } else {
 #define SDBIE_STO(T, DL, SL, SUB, SLIP) \
-    launch_pair_kernels<StokesOp<T, DL, SL, SUB, SLIP>, T>(P, a, st, 1, code, d.mixed)
+    sym = launch_pair_kernels<StokesOp<T, DL, SL, SUB, SLIP>, T>(P, a, st, 1, code, d.mixed)
         if (!d.mixed) {
             switch (code) {
                 case 1: SDBIE_STO(double, true, false, false, false); break;
@@ -1207,13 +1519,7 @@ void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
         }
 #undef SDBIE_STO
     }
-    const double* add = d.add_const;
-    hipLaunchKernelGGL((epilogue<3>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P.n, 2 * S,
-                       (const double*)P.partial, d.target_weight ? (const double*)P.w : nullptr, d.base,
-                       d.base_scale, d.comp, d.comp_scale,
-                       (const double*)P.nrm, add ? add[0] : 0.0, add ? add[1] : 0.0, add ? add[2] : 0.0,
-                       d.out, d.scatter ? (const int32_t*)P.perm : nullptr);
-    SDBIE_LAUNCHED();
+    launch_epilogue<3>(P, d, S, sym, st);
     Plan& Pm = const_cast<Plan&>(P);
     (d.mixed ? Pm.applies_mixed : Pm.applies_fp64) += 1;
     Pm.pairs += (double)P.n * (double)P.n;

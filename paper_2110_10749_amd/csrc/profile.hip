@@ -28,28 +28,51 @@ std::vector<Rec> g_recs;
 
 }  // namespace
 
-// variant = ((family * 4 + part) * 2 + mixed) * 32 + code
+// variant = ((family * 8 + part) * 2 + mixed) * 32 + code
 // family: 0 Laplace, 1 Stokes, 2 position gradient; part: 0 far kernel,
 // 1 near kernel, 2 source-record packing, 3 far and near blocks in one
-// launch; code: DL 1, SL 2, SUB 4, SLIP 8,
-// transposed (target normal) 16.
+// launch, 4 the same with a target-source symmetric far field; code: DL 1,
+// SL 2, SUB 4, SLIP 8, transposed (target normal) 16.
 int prof_variant(int family, bool mixed, int code, int part) {
-    return ((family * 4 + part) * 2 + (mixed ? 1 : 0)) * 32 + code;
+    return ((family * 8 + part) * 2 + (mixed ? 1 : 0)) * 32 + code;
 }
 
 namespace {
 void decode(int v, int& family, int& part, int& mixed, int& code) {
     code = v & 31;
     mixed = (v >> 5) & 1;
-    part = (v >> 6) & 3;
-    family = v >> 8;
+    part = (v >> 6) & 7;
+    family = v >> 9;
+}
+
+// Flops of one unordered far pair in the symmetric form (both directions,
+// the shared geometry once), halved: per ordered pair.
+double symmetric_flops_per_pair(int family, bool dl, bool sl, bool sub) {
+    const double common = 9.0;  // D (3), r^2 (5), rsqrt (1)
+    double f = common;
+    if (family == 0) {
+        if (dl) f += 2 + 5 + 5 + 4;  // k2, D.n_s, D.n_t, the two products with (q_s - q_t) or q
+        if (sl) f += 4;              // g_s k1, g_t k1
+        f += 2;                      // the two accumulations
+        return 0.5 * f;
+    }
+    f += 1;  // 1/r^2
+    if (dl) f += (sub ? 3 : 0) + 5 + (sub ? 0 : 6) + 5 + 5;  // u_s - u_t, ud, ud' (no subtraction), D.n_s, D.n_t
+    if (sl) {
+        f += 1 + 5 + 5 + (dl ? 6 : 2);  // 1/r^3, D.f_s, D.f_t, the two coefficients
+        f += 12 + 9;                    // forward 1/r f_s + e D, reverse 1/r f_t + e D
+    } else {
+        f += 2 + 4 + 6 + 3;  // 1/r^5, the two coefficients, e D forward and reverse
+    }
+    f += 3;  // the reverse additions
+    return 0.5 * f;
 }
 }  // namespace
 
 std::string prof_name(int v) {
     int family, part, mixed, code;
     decode(v, family, part, mixed, code);
-    static const char* parts[] = {"far", "near", "pack", "pass"};
+    static const char* parts[] = {"far", "near", "pack", "pass", "sympass", "?", "?", "?"};
     std::string s = family == 0 ? "laplace" : family == 1 ? "stokes" : "position_gradient";
     if (code & 16) s += "_T";
     s += std::string("_") + parts[part] + "<" + (mixed ? "f32" : "f64");
@@ -70,6 +93,7 @@ double flops_per_pair(int v) {
     decode(v, family, part, mixed, code);
     const bool dl = code & 1, sl = code & 2, sub = code & 4;
     if (family == 2 || part == 2) return 0.0;  // gradient: not counted
+    if (part == 4) return symmetric_flops_per_pair(family, dl, sl, sub);
     // common: D (3), r^2 (1 mul + 2 fma = 5), rsqrt (1)
     const double common = 9.0;
     if (code & 16) {

@@ -27,23 +27,28 @@ namespace sdbie {
 // Computations", section 7.5): each step chases the bulge of the implicit
 // double shift down the active window with Householder reflectors of three
 // elements (two at the end), applied only inside the window since only the
-// eigenvalues are wanted; a subdiagonal entry below DBL_EPSILON times its two
-// diagonal neighbours deflates the window, and 1x1 and 2x2 trailing blocks
-// give their eigenvalues in closed form.  Ad hoc shifts after 10 and 20 steps
-// without deflation break cycles.  Returns false if one eigenvalue needs more
-// than 100 steps.
+// eigenvalues are wanted; a subdiagonal entry below DBL_EPSILON times the
+// larger of its two diagonal neighbours' sum and the largest entry of the
+// matrix deflates the window, and 1x1 and 2x2 trailing blocks
+// give their eigenvalues in closed form.  A real pair of shifts is replaced by
+// the one closer to the last diagonal entry, taken twice, and ad hoc shifts
+// after 10 and 20 steps without deflation break cycles (both as in LAPACK's
+// small-matrix QR).  Returns false if one eigenvalue needs more than 100
+// steps.
 bool hessenberg_eigenvalues(int n, double* A, double* wr, double* wi) {
     auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
-    double anorm = 0.0;
+    double hmax = 0.0;  // largest entry: the scale of the normwise deflation test
     for (int i = 0; i < n; ++i)
-        for (int j = (i > 0 ? i - 1 : 0); j < n; ++j) anorm += std::fabs(a(i, j));
+        for (int j = (i > 0 ? i - 1 : 0); j < n; ++j) hmax = std::fmax(hmax, std::fabs(a(i, j)));
     int hi = n - 1, its = 0;
     while (hi >= 0) {
-        // deflation: the lowest l > 0 in the window with a negligible a(l, l-1)
+        // deflation: the lowest l > 0 in the window with a negligible a(l, l-1),
+        // below DBL_EPSILON times its diagonal neighbours or times the largest
+        // entry (normwise backward stable; the copies of one eigenvalue in a
+        // cluster leave subdiagonals a few ulps of that eigenvalue in size)
         int l = hi;
         for (; l > 0; --l) {
-            double sc = std::fabs(a(l - 1, l - 1)) + std::fabs(a(l, l));
-            if (sc == 0.0) sc = anorm;
+            const double sc = std::fmax(std::fabs(a(l - 1, l - 1)) + std::fabs(a(l, l)), hmax);
             if (std::fabs(a(l, l - 1)) <= DBL_EPSILON * sc) {
                 a(l, l - 1) = 0.0;
                 break;
@@ -78,15 +83,32 @@ bool hessenberg_eigenvalues(int n, double* A, double* wr, double* wi) {
             continue;
         }
         if (its >= 100) return false;
-        // the double shift: the eigenvalues of the trailing 2x2 block (sum s, product t)
+        // the double shift (sum s and product t of the two shifts): the
+        // eigenvalues of the trailing 2x2 block when they are complex; when
+        // they are real, twice the one closer to a(hi, hi).  The trailing
+        // block's own pair would annihilate the first column of the step
+        // whenever a block higher in the window has the same eigenvalues, as
+        // the copies of one eigenvalue that Arnoldi on a symmetric surface
+        // produces do; a repeated real shift does not.  Steps 10 and 20 take
+        // an ad hoc complex pair near a(hi, hi) instead.
         double s, t;
+        const double p = a(hi - 1, hi - 1), q = a(hi - 1, hi), r = a(hi, hi - 1), d = a(hi, hi);
         if (its == 10 || its == 20) {
             const double x = std::fabs(a(hi, hi - 1)) + std::fabs(a(hi - 1, hi - 2));
-            s = 1.5 * x;
-            t = x * x;
+            const double c = d + 0.75 * x;
+            s = 2.0 * c;
+            t = c * c + 0.4375 * x * x;
         } else {
-            s = a(hi - 1, hi - 1) + a(hi, hi);
-            t = a(hi - 1, hi - 1) * a(hi, hi) - a(hi - 1, hi) * a(hi, hi - 1);
+            const double mid = 0.5 * (p + d), half = 0.5 * (p - d), disc = half * half + q * r;
+            if (disc >= 0.0) {
+                const double root = std::sqrt(disc);
+                const double sig = std::fabs(mid + root - d) <= std::fabs(mid - root - d) ? mid + root : mid - root;
+                s = 2.0 * sig;
+                t = sig * sig;
+            } else {
+                s = p + d;
+                t = p * d - q * r;
+            }
         }
         ++its;
         // first column of (A - s1 I)(A - s2 I) = A^2 - s A + t I (rows l .. l+2)
@@ -111,10 +133,10 @@ bool hessenberg_eigenvalues(int n, double* A, double* wr, double* wi) {
             const double beta = 2.0 / uu;
             // from the left: rows k .. k+len-1, columns from the bulge's column to hi
             for (int j = (k > l ? k - 1 : l); j <= hi; ++j) {
-                double d = 0.0;
-                for (int i = 0; i < len; ++i) d += u[i] * a(k + i, j);
-                d *= beta;
-                for (int i = 0; i < len; ++i) a(k + i, j) -= d * u[i];
+                double dot = 0.0;
+                for (int i = 0; i < len; ++i) dot += u[i] * a(k + i, j);
+                dot *= beta;
+                for (int i = 0; i < len; ++i) a(k + i, j) -= dot * u[i];
             }
             if (k > l) {  // the reflector zeroed the bulge below a(k, k-1)
                 a(k, k - 1) = alpha;
@@ -123,10 +145,10 @@ bool hessenberg_eigenvalues(int n, double* A, double* wr, double* wi) {
             // from the right: columns k .. k+len-1, rows l .. min(k+3, hi)
             const int rmax = k + 3 < hi ? k + 3 : hi;
             for (int i = l; i <= rmax; ++i) {
-                double d = 0.0;
-                for (int j = 0; j < len; ++j) d += a(i, k + j) * u[j];
-                d *= beta;
-                for (int j = 0; j < len; ++j) a(i, k + j) -= d * u[j];
+                double dot = 0.0;
+                for (int j = 0; j < len; ++j) dot += a(i, k + j) * u[j];
+                dot *= beta;
+                for (int j = 0; j < len; ++j) a(i, k + j) -= dot * u[j];
             }
         }
     }

@@ -13,6 +13,8 @@
 // nodes (double and float) for the pair kernels; per-tile bounding boxes and
 // the near-field masks of tile pairs (box distance below rho_cut delta, one
 // mask for the double cutoff and one for the float cutoff).
+#include <vector>
+
 #include "smoothing_coeffs.h"
 #include "solver.h"
 
@@ -186,6 +188,60 @@ __global__ void k_near_masks(int nt, int64_t n, const double* __restrict__ boxes
     }
 }
 
+// Work lists of the symmetric far field, from the near masks (host side):
+// the far tile pairs {a < b} numbered column by column (pair p of column b
+// owns a reverse-partial slot of source tile b; rev_start[b] is the first),
+// and the same pairs as work items (a, b, p) row by row, cut into blocks of at
+// most kSymChunk items of one target tile a (fwd_start[a] is its first block).
+void build_symmetric_lists(Plan& P, hipStream_t st) {
+    const int T = P.ntiles;
+    std::vector<uint8_t> m((size_t)T * T);
+    std::vector<int32_t> pid((size_t)T * T, -1), rev_start(T + 1), fwd_start(T + 1), items, blocks;
+    for (int k = 0; k < 2; ++k) {
+        SDBIE_HIP(hipMemcpyAsync(m.data(), k ? P.mask32 : P.mask64, m.size(), hipMemcpyDeviceToHost, st));
+        SDBIE_HIP(hipStreamSynchronize(st));
+        int np = 0;
+        for (int b = 0; b < T; ++b) {
+            rev_start[b] = np;
+            for (int a = 0; a < b; ++a)
+                if (!m[(size_t)a * T + b]) pid[(size_t)a * T + b] = np++;
+        }
+        rev_start[T] = np;
+        items.clear();
+        blocks.clear();
+        for (int a = 0; a < T; ++a) {
+            fwd_start[a] = (int32_t)(blocks.size() / 2);
+            int cnt = 0;
+            for (int b = a + 1; b < T; ++b) {
+                if (m[(size_t)a * T + b]) continue;
+                if (cnt == 0) {
+                    blocks.push_back((int32_t)(items.size() / 3));
+                    blocks.push_back(0);
+                }
+                items.push_back(a);
+                items.push_back(b);
+                items.push_back(pid[(size_t)a * T + b]);
+                ++blocks.back();
+                if (++cnt == kSymChunk) cnt = 0;
+            }
+        }
+        fwd_start[T] = (int32_t)(blocks.size() / 2);
+        P.sym_npairs[k] = np;
+        P.sym_nblocks[k] = (int)(blocks.size() / 2);
+        if (np > 0) {
+            SDBIE_HIP(hipMemcpyAsync(P.sym_items[k], items.data(), items.size() * sizeof(int32_t),
+                                     hipMemcpyHostToDevice, st));
+            SDBIE_HIP(hipMemcpyAsync(P.sym_blocks[k], blocks.data(), blocks.size() * sizeof(int32_t),
+                                     hipMemcpyHostToDevice, st));
+        }
+        SDBIE_HIP(hipMemcpyAsync(P.sym_fwd_start[k], fwd_start.data(), (T + 1) * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, st));
+        SDBIE_HIP(hipMemcpyAsync(P.sym_rev_start[k], rev_start.data(), (T + 1) * sizeof(int32_t),
+                                 hipMemcpyHostToDevice, st));
+        SDBIE_HIP(hipStreamSynchronize(st));  // the host vectors are reused
+    }
+}
+
 }  // namespace
 
 void stage_surface(Plan& P, const sdbie_surface* s, hipStream_t st) {
@@ -242,6 +298,7 @@ void stage_surface(Plan& P, const sdbie_surface* s, hipStream_t st) {
     SDBIE_HIP(hipStreamSynchronize(st));
     P.near_pairs64 = (double)hc[0];
     P.near_pairs32 = (double)hc[1];
+    if (P.sym_items[0]) build_symmetric_lists(P, st);
     dev_dot(P, P.w, nullptr, n, P.scal + kScalStage + 8, st);
     P.area = host_read_scalar(P.scal + kScalStage + 8, st);
     if (!(P.area > 0.0)) throw Error(SDBIE_ERR_ARG, "the quadrature weights sum to zero");

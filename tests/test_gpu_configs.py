@@ -107,6 +107,8 @@ def test_sphere_parameter_grid_h64(sd, sphere64, K, alpha):
 def make_surface(kind, h):
     if kind == "ellipsoid":
         return surfaces.ellipsoid(h, 1.0, 0.8, 0.6)
+    if kind == "thin_ellipsoid":
+        return surfaces.ellipsoid(h, 1.0, 0.6, 0.4)
     return surfaces.perturbed_sphere(h, lmax=4, sigma=0.05, seed=0)
 
 
@@ -131,12 +133,20 @@ def common_nodes(xa, xb):
     return np.array(ia), np.array(ib)
 
 
-@pytest.mark.parametrize("kind", ["ellipsoid", "perturbed"])
+@pytest.mark.parametrize("kind", ["ellipsoid", "perturbed", "thin_ellipsoid"])
 def test_layers_sampled_rows(sd, kind):
+    # the thin ellipsoid (1, .6, .4) of the paper's Table 3 as well (N = 27566)
     S = make_surface(kind, 1.0 / 64)
     rng = np.random.default_rng(21)
     t = np.sort(rng.choice(S.N, size=192, replace=False))
     check_all_layers(sd, S.x, S.n, S.w, 3.0 / 64, seed=22, targets=t)
+
+
+def test_layers_molecule_all_rows(sd):
+    # the four-atom surface of eq. (Molecule) at h = 1/32 (N = 9562): every
+    # layer kind in both precisions against the oracle on every row
+    S = surfaces.molecule(1.0 / 32)
+    check_all_layers(sd, S.x, S.n, S.w, 3.0 / 32, seed=23)
 
 
 @pytest.mark.parametrize("kind", ["ellipsoid", "perturbed"])

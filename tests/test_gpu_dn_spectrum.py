@@ -19,11 +19,14 @@ T_lin (eq. (A_mat), section "Discrete iteration operator"), as in the paper's
 figure of them (h = 1/16, N = 4302; kappa = 1 with theta = 0.5, 0.75; kappa =
 1e-2, 1e-4 with theta = c kappa, c = 0.5, 0.75, 0.9): the GPU's Arnoldi on
 T_lin (ddm_dn_spectrum, 240 steps, local solves to 1e-13) gives Ritz values
-whose leading 48 (the complete multiplets n = 1..6) match the eigenvalues of
-the oracle's dense A~ (tests/golden/oracle_spectrum_h16.json, written by
+whose leading 50 (as the figure shows) match the eigenvalues of the oracle's
+dense A~ (tests/golden/oracle_spectrum_h16.json, written by
 tests/golden/make_oracle_spectrum.py) to 1e-8 of their spread, and each
-multiplet of 2n + 1 lies at the closed-form lambda_n within the
-discretisation error of h = 1/16.
+multiplet of 2n + 1 (n = 1..6, the first 48) lies at the closed-form
+lambda_n within the discretisation error of h = 1/16 (twice the oracle's
+own deviations: 6.5e-5, 9.2e-4, 3.7e-3, 1.0e-2, 2.3e-2, 4.5e-2).  Arnoldi
+on the oracle's dense T_lin from the same start converges the leading 60
+to rounding within 180 steps.
 """
 import json
 import os
@@ -113,7 +116,7 @@ def test_iteration_matrix_eigenvalues_h16(sd, sphere16, K, prec):
     print(f"K={K:g} {prec}: {info['ddm_iters']} Arnoldi steps, {info['gmres_iters']} local GMRES iterations; "
           f"leading Ritz values {np.round(lam[:4].real, 8)}", flush=True)
     assert info["converged"] and info["ddm_iters"] == 240
-    assert np.max(np.abs(lam[:48].imag)) < 1e-8 * np.max(np.abs(lam))
+    assert np.max(np.abs(lam[:50].imag)) < 1e-8 * np.max(np.abs(lam))
     # multiplets of the degree-n harmonics at the closed-form lambda_n
     start = 0
     for n in range(1, 7):
@@ -131,7 +134,7 @@ def test_iteration_matrix_eigenvalues_h16(sd, sphere16, K, prec):
         ref = np.array(c["re"]) + 1j * np.array(c["im"])
         got = (1.0 - theta) + theta * lam
         spread = np.max(np.abs(ref - (1.0 - theta)))
-        err = np.max(np.abs(got[:48] - ref[:48])) / spread
+        err = np.max(np.abs(got[:50] - ref[:50])) / spread
         print(f"  theta={theta:g}: A~ eigenvalues {np.round(got[:3].real, 6)} ... vs oracle {err:.1e} "
               f"(50th: {got[49].real:.8f} vs {ref[49].real:.8f})", flush=True)
         assert err < 1e-8

@@ -10,8 +10,8 @@ the unit sphere's (the four-atom surface gives errors 30-60 times larger), so it
 is checked on the sphere.  Rows kappa = 1 and 1e-2; the printed values have 4
 digits and the GPU values agree to them (tolerance 0.3%).  The four-atom
 surface itself is checked for the convergence order the paper states for its
-solutions (about h^5): each halving of h divides the differences by more than
-12 (measured 19-26).  Solves at local
+solutions (about h^5): each halving of h from 1/16 to 1/128 divides the
+differences by more than 12.  Solves at local
 tolerance 1e-11 and interface tolerance 1e-10, far below the differences.
 """
 import numpy as np
@@ -87,7 +87,10 @@ def test_table4_is_the_sphere(sd, golden, row):
 
 @pytest.mark.parametrize("K", [1.0, 1e-2])
 def test_molecule_self_convergence(sd, K):
-    errs = self_convergence(sd, surfaces.molecule, [16, 32, 64], K)
+    errs = self_convergence(sd, surfaces.molecule, [16, 32, 64, 128], K)
     print(f"K={K:g} molecule: {errs}", flush=True)
-    (p16, u16), (p32, u32) = errs[16], errs[32]
-    assert p16 / p32 > 12.0 and u16 / u32 > 12.0
+    # errs[h]: differences between the solutions at h and h/2
+    for a, b in ((16, 32), (32, 64)):
+        (pa, ua), (pb, ub) = errs[a], errs[b]
+        print(f"  differences (1/{a}, 1/{2 * a}) / (1/{b}, 1/{2 * b}): p {pa / pb:.1f}, u {ua / ub:.1f}", flush=True)
+        assert pa / pb > 12.0 and ua / ub > 12.0

@@ -318,3 +318,72 @@ def test_translated_body_float_pairs(sd):
         plan.close()
     assert rel(out["moved"][1], out["origin"][1]) < 1e-9
     assert rel(out["moved"][0], out["origin"][0]) < 1e-7
+
+
+@pytest.mark.parametrize("local", ["sa", "gmres"])
+def test_table1_h32_row(sd, golden, local):
+    # Table 1, row h = 1/32 (N = 17070), kappa = 1, no slip, the exact viscous
+    # traction added: the D-N relaxation counts at theta = 0.5 and 0.75 with the
+    # paper's tolerances (1e-9 for the interface residual and the local solves,
+    # successive approximations or GMRES locally), and the printed errors of
+    # p_D and u_S (4 digits) at the discrete fixed point (tight tolerances)
+    S = surfaces.sphere(1.0 / 32)
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / 32)
+    ref = golden["table1_h32"]
+    fx = dev(exact.jt_viscous_traction(S.x, E, K=1.0))
+    for theta, key in ((0.5, "dn_sa_theta05"), (0.75, "dn_sa_theta075")):
+        opts = dict(outer="sa", theta=theta, tol_gmres=1e-9, tol_ddm=1e-9, local_solver=local, maxit_gmres=1000)
+        p, u, D, info = sd.ddm_solve(plan, 1.0, 1.0, 0.0, E, fx, opts=opts)
+        print(local, theta, info, flush=True)
+        assert info["converged"] and info["ddm_iters"] - 1 == ref[key]
+    tight = dict(outer="sa", theta=0.75, tol_gmres=1e-13, tol_ddm=1e-12, local_solver=local, maxit_gmres=3000)
+    p, u, D, info = sd.ddm_solve(plan, 1.0, 1.0, 0.0, E, fx, opts=tight)
+    ep = rms(host(p) - exact.jt_pressure(S.x, E, K=1.0))
+    eu = rms(host(u) - exact.jt_velocity(S.x, E, K=1.0))
+    print(local, f"errors p {ep:.4e} u {eu:.4e} (printed {ref['err_p']:.3e}, {ref['err_u']:.3e})", flush=True)
+    assert info["converged"]
+    assert float(f"{ep:.3e}") == ref["err_p"] and float(f"{eu:.3e}") == ref["err_u"]
+    plan.close()
+
+
+def test_table1_h64_row(sd, golden):
+    # Table 1, row h = 1/64 (N = 68166): 2 D-N relaxation steps at theta = 0.75
+    # with the paper's tolerances (local GMRES; the table has no local SA entry
+    # at this size), and the printed errors of p_D and u_S at the discrete
+    # fixed point
+    S = surfaces.sphere(1.0 / 64)
+    plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / 64)
+    ref = golden["table1_h64"]
+    fx = dev(exact.jt_viscous_traction(S.x, E, K=1.0))
+    p, u, D, info = sd.ddm_solve(plan, 1.0, 1.0, 0.0, E, fx,
+                                 opts=dict(outer="sa", theta=0.75, tol_gmres=1e-9, tol_ddm=1e-9))
+    print(info, flush=True)
+    assert info["converged"] and info["ddm_iters"] - 1 == ref["dn_sa_theta075"]
+    p, u, D, info = sd.ddm_solve(plan, 1.0, 1.0, 0.0, E, fx,
+                                 opts=dict(outer="sa", theta=0.75, tol_gmres=1e-13, tol_ddm=1e-12))
+    ep = rms(host(p) - exact.jt_pressure(S.x, E, K=1.0))
+    eu = rms(host(u) - exact.jt_velocity(S.x, E, K=1.0))
+    print(f"errors p {ep:.4e} u {eu:.4e} (printed {ref['err_p']:.3e}, {ref['err_u']:.3e})", flush=True)
+    assert info["converged"]
+    assert float(f"{ep:.3e}") == ref["err_p"] and float(f"{eu:.3e}") == ref["err_u"]
+    plan.close()
+
+
+@pytest.mark.parametrize("K", [1e-2, 1e-4])
+def test_table2_relaxation_exceeds_100_iterations(sd, s16, golden, K):
+    # Table 2: with theta = c kappa (c = 0.5, 0.75) the relaxed D-N iteration
+    # needs more than 100 iterations to reach the residual 1e-9 of eq.
+    # (DDM_residual) for kappa = 1e-2 and 1e-4 (the iteration matrix has most of
+    # its eigenvalues near 1 - theta); D-N by GMRES converges in a few
+    S, geo, ops, plan = s16
+    cap = golden["table2_dn_sa_exceeds"]["iterations"]
+    fx = dev(exact.jt_viscous_traction(S.x, E, K=K))
+    for c in (0.5, 0.75):
+        opts = dict(outer="sa", theta=c * K, tol_gmres=1e-9, tol_ddm=1e-9, maxit_ddm=cap)
+        p, u, D, info = sd.ddm_solve(plan, 1.0, K, 0.0, E, fx, opts=opts)
+        print(f"K={K:g} theta={c}K: relaxation after {info['ddm_iters']} iterations: residual {info['ddm_res']:.2e}",
+              flush=True)
+        assert not info["converged"] and info["ddm_iters"] == cap and info["ddm_res"] > 1e-9
+    p, u, D, info = sd.ddm_solve(plan, 1.0, K, 0.0, E, fx, opts=dict(outer="gmres", tol_gmres=1e-9, tol_ddm=1e-9))
+    print(f"K={K:g}: D-N by GMRES {info['ddm_iters']} iterations", flush=True)
+    assert info["converged"] and info["ddm_iters"] <= 30

@@ -88,3 +88,31 @@ def test_perturbed_sphere_normals_match_finite_differences():
     chord = x[:, j] - x[:, i]
     cos = np.abs((chord * n[:, i]).sum(0)) / np.linalg.norm(chord, axis=0)
     assert np.median(cos) < 0.1
+
+
+def test_molecule_node_count_nesting_and_volume():
+    # the four-atom surface of eq. (Molecule): centres x_1 = (sqrt3/3, 0, -sqrt6/12),
+    # x_2,3 = (-sqrt3/6, +-0.5, -sqrt6/12), x_4 = (0, 0, sqrt6/4), r = 0.5, c = 0.6.
+    # 2392 nodes at h = 1/16 (the table's N column repeats the sphere's); the
+    # nodes at h are nodes at h/2 (the same grid lines); the volume from the
+    # quadrature by the divergence theorem, (1/3) sum w x.n, against a brute-force
+    # count of the points of a fine cubic lattice inside the surface
+    a = surfaces.molecule(1.0 / 16)
+    b = surfaces.molecule(1.0 / 32)
+    assert a.N == 2392
+    key = lambda x: set(map(tuple, np.round(x.T, 11)))
+    assert key(a.x) <= key(b.x)
+    assert np.allclose(np.linalg.norm(b.n, axis=0), 1.0, atol=1e-14)
+    assert np.abs((b.w * b.n).sum(axis=1)).max() < 2e-4
+    s3, s6 = math.sqrt(3.0), math.sqrt(6.0)
+    ctr = np.array([[s3 / 3, 0.0, -s6 / 12], [-s3 / 6, 0.5, -s6 / 12], [-s3 / 6, -0.5, -s6 / 12], [0.0, 0.0, s6 / 4]])
+    g = 1.0 / 160
+    t = np.arange(-1.3, 1.3 + g / 2, g)
+    inside = 0
+    for x0 in t:  # one plane at a time
+        X, Y, Z = np.meshgrid(np.array([x0]), t, t, indexing="ij")
+        s = sum(np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / 0.25) for c in ctr)
+        inside += int((s > 0.6).sum())
+    vol_grid = inside * g**3
+    vol_quad = (b.w * (b.x * b.n).sum(axis=0)).sum() / 3
+    assert abs(vol_quad - vol_grid) < 1e-4 * vol_grid, (vol_quad, vol_grid)  # measured 2.8e-5

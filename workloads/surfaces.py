@@ -207,7 +207,7 @@ def _implicit_surface(phi, grad_phi, h, extent, shell=None, dt_factor=0.5, lip=N
         if shell is None:
             t_lo = np.full(a.shape, -extent)
             t_hi = np.full(a.shape, extent)
-            li, t = _bracket_roots(phi, i, a, b, t_lo, t_hi, h * dt_factor, grad_phi)
+            li, t = _bracket_roots(phi, i, a, b, t_lo, t_hi, h * dt_factor, grad_phi, lip=lip)
         else:
             rmin, rmax = shell
             q = a * a + b * b
@@ -418,6 +418,8 @@ def molecule(h: float) -> Surface:
         e, d = gsum(x)
         return (2.0 / r2) * (e[None] * d).sum(axis=1)
 
-    P, Nn = _implicit_surface(phi, grad_phi, h, 1.4, dt_factor=0.25)
+    # |d phi / dt| <= |grad phi| <= 4 max_s (2 s / r^2) exp(-s^2 / r^2) = 4 (sqrt(2)/r) exp(-1/2)
+    lip = 4.0 * math.sqrt(2.0 / r2) * math.exp(-0.5)
+    P, Nn = _implicit_surface(phi, grad_phi, h, 1.4, dt_factor=0.25, lip=lip)
     x, n, w = _assemble(P, Nn, h)
     return Surface(x, n, w, h, name="molecule")
