@@ -169,13 +169,22 @@ int64_t sdbie_plan_n(sdbie_plan plan);
 
 /* Target-source symmetric far field (section "Numerical Results", local
  * problems: the paper's code evaluates each pair of nodes once for both
- * directions).  on = 1: every later layer sum and solve on the plan (the
- * transposed sums of ddm_adjoint excepted) evaluates each tile pair whose
- * node pairs all lie beyond the smoothing cutoff once, adding its
- * contributions to the targets of both tiles; near tile pairs stay one pass
- * per direction.  Same sums up to rounding.  on = 0 (the default): every
- * ordered pair in its own pass.  ERR_ARG for a null plan or on not 0/1. */
-int sdbie_plan_set_symmetric(sdbie_plan plan, int on);
+ * directions).  `families` is a mask of SDBIE_SYM_LAPLACE (the Laplace single
+ * and double layer passes) and SDBIE_SYM_STOKES (the Stokes passes): in every
+ * later layer sum and solve on the plan (the transposed sums of ddm_adjoint
+ * excepted) a pass of a selected family evaluates each tile pair whose node
+ * pairs all lie beyond the smoothing cutoff once, adding its contributions to
+ * the targets of both tiles; near tile pairs stay one pass per direction.
+ * Same sums up to rounding.  0: every ordered pair in its own pass.  The
+ * default, SDBIE_SYM_DEFAULT, selects the Laplace passes only: on gfx950 the
+ * symmetric Laplace passes are faster than the one-direction ones, the
+ * symmetric Stokes passes slower (their reverse sums move through cross-lane
+ * operations that issue at half rate).  ERR_ARG for a null plan or unknown
+ * bits. */
+#define SDBIE_SYM_LAPLACE 1
+#define SDBIE_SYM_STOKES 2
+#define SDBIE_SYM_DEFAULT SDBIE_SYM_LAPLACE
+int sdbie_plan_set_symmetric(sdbie_plan plan, int families);
 
 /* out = layer sum of `dens` (device, [n] for Laplace, [3][n] for Stokes, in
  * the caller's node order) at every node.  out must not alias dens.

@@ -185,6 +185,12 @@ def workspace_bytes(n: int, max_restart: int = 50) -> int:
     return int(lib().sdbie_workspace_bytes(n, max_restart))
 
 
+# pass families of sdbie_plan_set_symmetric (SDBIE_SYM_*)
+SYM_LAPLACE = 1
+SYM_STOKES = 2
+SYM_DEFAULT = SYM_LAPLACE
+
+
 class Plan:
     """A staged surface: node data copied into a device workspace in Morton order.
 
@@ -218,9 +224,16 @@ class Plan:
     def handle(self):
         return self._h
 
-    def set_symmetric(self, on: bool = True) -> None:
-        """Evaluate the far tile pairs once for both directions (sdbie_plan_set_symmetric)."""
-        _check(lib().sdbie_plan_set_symmetric(self._h, 1 if on else 0))
+    def set_symmetric(self, families=SYM_LAPLACE | SYM_STOKES) -> None:
+        """Evaluate the far tile pairs of the selected pass families once for
+        both directions (sdbie_plan_set_symmetric).  ``families``: a mask of
+        SYM_LAPLACE and SYM_STOKES; True means both, False neither.  A new plan
+        starts at SYM_DEFAULT."""
+        if families is True:
+            families = SYM_LAPLACE | SYM_STOKES
+        elif families is False:
+            families = 0
+        _check(lib().sdbie_plan_set_symmetric(self._h, int(families)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

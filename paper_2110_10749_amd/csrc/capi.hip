@@ -349,11 +349,11 @@ int sdbie_plan_destroy(sdbie_plan plan) {
 
 int64_t sdbie_plan_n(sdbie_plan plan) { return plan ? reinterpret_cast<Plan*>(plan)->n : -1; }
 
-int sdbie_plan_set_symmetric(sdbie_plan plan, int on) {
+int sdbie_plan_set_symmetric(sdbie_plan plan, int families) {
     return guarded([&]() -> int {
         Plan& P = plan_of(plan);
-        if (on != 0 && on != 1) fail(SDBIE_ERR_ARG, "on must be 0 or 1");
-        P.symmetric = on == 1;
+        if (families & ~(SDBIE_SYM_LAPLACE | SDBIE_SYM_STOKES)) fail(SDBIE_ERR_ARG, "unknown pass family bits");
+        P.symmetric = families;
         return SDBIE_OK;
     });
 }

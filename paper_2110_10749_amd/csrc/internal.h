@@ -141,12 +141,13 @@ struct Plan {
     double* host_pinned = nullptr;  // not used (host buffers are plain)
     // (target, source) pairs of real nodes in the near tile pairs (double, float masks)
     double near_pairs64 = 0.0, near_pairs32 = 0.0;
-    // target-source symmetric far field (used when `symmetric` is set): per
+    // target-source symmetric far field (for the pass families whose
+    // SDBIE_SYM_* bit is set in `symmetric`): per
     // precision (index 0 double, 1 float) the far tile pairs {a < b} numbered
     // in column order (pair p owns a reverse slot), the work items (a, b, p) in
     // row order cut into blocks of at most kSymChunk items, the first block of
     // each target tile and the first pair of each source tile
-    bool symmetric = false;
+    int symmetric = SDBIE_SYM_DEFAULT;
     int32_t* sym_items[2] = {};      // [npairs][3]
     int32_t* sym_blocks[2] = {};     // [nblocks][2]: first item, item count
     int32_t* sym_fwd_start[2] = {};  // [ntiles + 1]

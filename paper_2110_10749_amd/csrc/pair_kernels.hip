@@ -1058,6 +1058,7 @@ template <typename T, bool DL, bool SL, bool SUB>
 struct SymLaplace {
     using Op = LaplaceOp<T, DL, SL, SUB>;
     static constexpr int C = 1, R = Op::R;
+    static constexpr int kFamilyBit = SDBIE_SYM_LAPLACE;
     static constexpr int Q = Op::Q, NX = Op::NX, NY = Op::NY, NZ = Op::NZ, G = Op::G;
     template <int K>
     __device__ __forceinline__ static void step(const T (&tr)[R], const T (&sr)[R], T (&acc)[C], T (&racc)[C]) {
@@ -1098,6 +1099,7 @@ template <typename T, bool DL, bool SL, bool SUB, bool SLIP>
 struct SymStokes {
     using Op = StokesOp<T, DL, SL, SUB, SLIP>;
     static constexpr int C = 3, R = Op::R;
+    static constexpr int kFamilyBit = SDBIE_SYM_STOKES;
     static constexpr int NX = Op::NX, NY = Op::NY, NZ = Op::NZ, UX = Op::UX, UY = Op::UY, UZ = Op::UZ;
     static constexpr int FX = Op::FX, FY = Op::FY, FZ = Op::FZ;
     template <int K>
@@ -1322,7 +1324,7 @@ bool launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int fami
     using Sym = typename SymOf<Op>::type;
     if constexpr (!std::is_same<Sym, void>::value) {
         const int k = mixed ? 1 : 0;
-        if (P.symmetric && P.sym_items[k] && P.sym_nblocks[k] > 0 && !a.dl_tgt) {
+        if ((P.symmetric & Sym::kFamilyBit) && P.sym_items[k] && P.sym_nblocks[k] > 0 && !a.dl_tgt) {
             SymArgs sa;
             sa.nblocks = P.sym_nblocks[k];
             sa.items = P.sym_items[k];

@@ -22,135 +22,173 @@
 
 namespace sdbie {
 
+// The double shift of one QR step from a 2x2 block [[h11, h12], [h21, h22]]:
+// its eigenvalues when they are complex (sh = re, im, re, -im); when they are
+// real, twice the one closer to h22 (a trailing block's own pair of real
+// shifts would annihilate the first column of the step whenever a block
+// higher in the window has the same eigenvalues, as the copies of one
+// eigenvalue that Arnoldi on a symmetric surface produces do).  The block is
+// scaled to unit size first.
+static void double_shift(double h11, double h12, double h21, double h22, double sh[4]) {
+    const double sc = std::fabs(h11) + std::fabs(h12) + std::fabs(h21) + std::fabs(h22);
+    if (sc == 0.0) {
+        sh[0] = sh[1] = sh[2] = sh[3] = 0.0;
+        return;
+    }
+    h11 /= sc;
+    h12 /= sc;
+    h21 /= sc;
+    h22 /= sc;
+    const double tr = 0.5 * (h11 + h22);
+    const double det = (h11 - tr) * (h22 - tr) - h12 * h21;
+    const double rt = std::sqrt(std::fabs(det));
+    if (det >= 0.0) {
+        sh[0] = sh[2] = tr * sc;
+        sh[1] = rt * sc;
+        sh[3] = -rt * sc;
+    } else {
+        const double r1 = tr + rt, r2 = tr - rt;
+        sh[0] = sh[2] = (std::fabs(r1 - h22) <= std::fabs(r2 - h22) ? r1 : r2) * sc;
+        sh[1] = sh[3] = 0.0;
+    }
+}
+
 // Eigenvalues of an upper Hessenberg matrix A (n x n, row-major; overwritten)
 // by the Francis double-shift QR iteration (Golub and Van Loan, "Matrix
-// Computations", section 7.5): each step chases the bulge of the implicit
-// double shift down the active window with Householder reflectors of three
-// elements (two at the end), applied only inside the window since only the
-// eigenvalues are wanted; a subdiagonal entry below DBL_EPSILON times the
-// larger of its two diagonal neighbours' sum and the largest entry of the
-// matrix deflates the window, and 1x1 and 2x2 trailing blocks
-// give their eigenvalues in closed form.  A real pair of shifts is replaced by
-// the one closer to the last diagonal entry, taken twice, and ad hoc shifts
-// after 10 and 20 steps without deflation break cycles (both as in LAPACK's
-// small-matrix QR).  Returns false if one eigenvalue needs more than 100
-// steps.
+// Computations", section 7.5), with the safeguards of LAPACK's small-matrix
+// QR: only the active window is transformed, since only the eigenvalues are
+// wanted; a subdiagonal entry deflates when it is negligible against its
+// diagonal neighbours in the sense of Ahues and Tisseur; the first column of
+// the double-shift polynomial is formed from the shifts themselves,
+// (a00 - s1)(a00 - s2) + a01 a10, never from their sum and product (for a
+// cluster of nearly equal eigenvalues a00^2 - s a00 + t cancels to noise and
+// the iteration stalls); a step starts below the top of the window where two
+// consecutive subdiagonal entries are small enough; ad hoc shifts every 10
+// steps without deflation break cycles; 1x1 and 2x2 blocks give their
+// eigenvalues in closed form.  Returns false if 30 max(10, n) steps pass
+// without a deflation.
 bool hessenberg_eigenvalues(int n, double* A, double* wr, double* wi) {
     auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
-    double hmax = 0.0;  // largest entry: the scale of the normwise deflation test
-    for (int i = 0; i < n; ++i)
-        for (int j = (i > 0 ? i - 1 : 0); j < n; ++j) hmax = std::fmax(hmax, std::fabs(a(i, j)));
-    int hi = n - 1, its = 0;
+    const double ulp = DBL_EPSILON, tiny = DBL_MIN;
+    const int itmax = 30 * (n > 10 ? n : 10);
+    int hi = n - 1;
     while (hi >= 0) {
-        // deflation: the lowest l > 0 in the window with a negligible a(l, l-1),
-        // below DBL_EPSILON times its diagonal neighbours or times the largest
-        // entry (normwise backward stable; the copies of one eigenvalue in a
-        // cluster leave subdiagonals a few ulps of that eigenvalue in size)
-        int l = hi;
-        for (; l > 0; --l) {
-            const double sc = std::fmax(std::fabs(a(l - 1, l - 1)) + std::fabs(a(l, l)), hmax);
-            if (std::fabs(a(l, l - 1)) <= DBL_EPSILON * sc) {
-                a(l, l - 1) = 0.0;
-                break;
+        int l = hi, kdefl = 0;
+        for (int its = 0;; ++its) {
+            // the lowest l > 0 with a negligible a(l, l-1), or 0
+            for (l = hi; l > 0; --l) {
+                const double sub = std::fabs(a(l, l - 1));
+                if (sub <= tiny) break;
+                double tst = std::fabs(a(l - 1, l - 1)) + std::fabs(a(l, l));
+                if (tst == 0.0) {
+                    if (l >= 2) tst += std::fabs(a(l - 1, l - 2));
+                    if (l + 1 <= hi) tst += std::fabs(a(l + 1, l));
+                }
+                if (sub <= ulp * tst) {
+                    const double up = std::fabs(a(l - 1, l));
+                    const double ab = std::fmax(sub, up), ba = std::fmin(sub, up);
+                    const double dd = std::fabs(a(l - 1, l - 1) - a(l, l));
+                    const double aa = std::fmax(std::fabs(a(l, l)), dd), bb = std::fmin(std::fabs(a(l, l)), dd);
+                    const double sc = aa + ab;
+                    if (ba * (ab / sc) <= std::fmax(tiny, ulp * (bb * (aa / sc)))) break;
+                }
+            }
+            if (l > 0) a(l, l - 1) = 0.0;
+            if (l >= hi - 1) break;  // a 1x1 or 2x2 block has split off
+            if (its >= itmax) return false;
+            ++kdefl;
+            double sh[4];
+            if (kdefl % 20 == 0) {  // ad hoc shift from the top of the window
+                const double x = std::fabs(a(l + 1, l)) + std::fabs(a(l + 2, l + 1));
+                const double c = 0.75 * x + a(l, l);
+                double_shift(c, -0.4375 * x, x, c, sh);
+            } else if (kdefl % 10 == 0) {  // from the bottom
+                const double x = std::fabs(a(hi, hi - 1)) + std::fabs(a(hi - 1, hi - 2));
+                const double c = 0.75 * x + a(hi, hi);
+                double_shift(c, -0.4375 * x, x, c, sh);
+            } else {
+                double_shift(a(hi - 1, hi - 1), a(hi - 1, hi), a(hi, hi - 1), a(hi, hi), sh);
+            }
+            // first column of (A - s1 I)(A - s2 I) at rows m .. m+2, scaled; the
+            // step starts at the lowest m whose a(m, m-1) it would barely touch
+            double v[3];
+            int m = hi - 2;
+            for (;; --m) {
+                const double h21 = a(m + 1, m);
+                double sc = std::fabs(a(m, m) - sh[2]) + std::fabs(sh[3]) + std::fabs(h21);
+                const double h21s = sc != 0.0 ? h21 / sc : 0.0;
+                if (sc == 0.0) sc = 1.0;
+                v[0] = h21s * a(m, m + 1) + (a(m, m) - sh[0]) * ((a(m, m) - sh[2]) / sc) - sh[1] * (sh[3] / sc);
+                v[1] = h21s * (a(m, m) + a(m + 1, m + 1) - sh[0] - sh[2]);
+                v[2] = h21s * a(m + 2, m + 1);
+                const double sv = std::fabs(v[0]) + std::fabs(v[1]) + std::fabs(v[2]);
+                if (sv != 0.0)
+                    for (double& x : v) x /= sv;
+                if (m == l) break;
+                const double h00 = std::fabs(a(m - 1, m - 1)) + std::fabs(a(m, m)) + std::fabs(a(m + 1, m + 1));
+                if (std::fabs(a(m, m - 1)) * (std::fabs(v[1]) + std::fabs(v[2])) <= ulp * std::fabs(v[0]) * h00) break;
+            }
+            // chase the bulge down the window with reflectors I - tau w w^T,
+            // w = (1, w1, w2), each mapping its vector onto beta e1
+            for (int k = m; k < hi; ++k) {
+                const int len = hi - k + 1 < 3 ? hi - k + 1 : 3;
+                if (k > m)
+                    for (int i = 0; i < len; ++i) v[i] = a(k + i, k - 1);
+                double xn = 0.0;
+                for (int i = 1; i < len; ++i) xn += v[i] * v[i];
+                xn = std::sqrt(xn);
+                double tau = 0.0, beta = v[0], w[3] = {1.0, 0.0, 0.0};
+                if (xn != 0.0) {
+                    beta = -std::copysign(std::hypot(v[0], xn), v[0]);
+                    tau = (beta - v[0]) / beta;
+                    for (int i = 1; i < len; ++i) w[i] = v[i] / (v[0] - beta);
+                }
+                if (k > m) {
+                    a(k, k - 1) = beta;
+                    for (int i = 1; i < len; ++i) a(k + i, k - 1) = 0.0;
+                } else if (m > l) {
+                    a(k, k - 1) *= 1.0 - tau;
+                }
+                if (tau == 0.0) continue;
+                for (int j = k; j <= hi; ++j) {  // from the left: rows k .. k+len-1
+                    double dot = 0.0;
+                    for (int i = 0; i < len; ++i) dot += w[i] * a(k + i, j);
+                    dot *= tau;
+                    for (int i = 0; i < len; ++i) a(k + i, j) -= dot * w[i];
+                }
+                const int rmax = k + 3 < hi ? k + 3 : hi;
+                for (int i = l; i <= rmax; ++i) {  // from the right: columns k .. k+len-1
+                    double dot = 0.0;
+                    for (int j = 0; j < len; ++j) dot += a(i, k + j) * w[j];
+                    dot *= tau;
+                    for (int j = 0; j < len; ++j) a(i, k + j) -= dot * w[j];
+                }
             }
         }
         if (l == hi) {  // a 1x1 block
             wr[hi] = a(hi, hi);
             wi[hi] = 0.0;
-            --hi;
-            its = 0;
+            hi -= 1;
             continue;
         }
-        if (l == hi - 1) {  // a 2x2 block [[p, q], [r, s]]
-            const double p = a(hi - 1, hi - 1), q = a(hi - 1, hi), r = a(hi, hi - 1), s = a(hi, hi);
-            const double mid = 0.5 * (p + s), half = 0.5 * (p - s);
-            const double disc = half * half + q * r;
-            if (disc >= 0.0) {
-                const double root = std::sqrt(disc);
-                const double l1 = mid + (mid >= 0.0 ? root : -root);  // the one of larger modulus
-                const double l2 = l1 != 0.0 ? (p * s - q * r) / l1 : mid - root;
-                wr[hi - 1] = l1;
-                wr[hi] = l2;
-                wi[hi - 1] = wi[hi] = 0.0;
-            } else {
-                const double root = std::sqrt(-disc);
-                wr[hi - 1] = wr[hi] = mid;
-                wi[hi - 1] = root;
-                wi[hi] = -root;
-            }
-            hi -= 2;
-            its = 0;
-            continue;
-        }
-        if (its >= 100) return false;
-        // the double shift (sum s and product t of the two shifts): the
-        // eigenvalues of the trailing 2x2 block when they are complex; when
-        // they are real, twice the one closer to a(hi, hi).  The trailing
-        // block's own pair would annihilate the first column of the step
-        // whenever a block higher in the window has the same eigenvalues, as
-        // the copies of one eigenvalue that Arnoldi on a symmetric surface
-        // produces do; a repeated real shift does not.  Steps 10 and 20 take
-        // an ad hoc complex pair near a(hi, hi) instead.
-        double s, t;
-        const double p = a(hi - 1, hi - 1), q = a(hi - 1, hi), r = a(hi, hi - 1), d = a(hi, hi);
-        if (its == 10 || its == 20) {
-            const double x = std::fabs(a(hi, hi - 1)) + std::fabs(a(hi - 1, hi - 2));
-            const double c = d + 0.75 * x;
-            s = 2.0 * c;
-            t = c * c + 0.4375 * x * x;
+        // a 2x2 block [[p, q], [r, s]]
+        const double p = a(hi - 1, hi - 1), q = a(hi - 1, hi), r = a(hi, hi - 1), s = a(hi, hi);
+        const double mid = 0.5 * (p + s), half = 0.5 * (p - s);
+        const double disc = half * half + q * r;
+        if (disc >= 0.0) {
+            const double root = std::sqrt(disc);
+            const double l1 = mid + (mid >= 0.0 ? root : -root);  // the one of larger modulus
+            const double l2 = l1 != 0.0 ? (p * s - q * r) / l1 : mid - root;
+            wr[hi - 1] = l1;
+            wr[hi] = l2;
+            wi[hi - 1] = wi[hi] = 0.0;
         } else {
-            const double mid = 0.5 * (p + d), half = 0.5 * (p - d), disc = half * half + q * r;
-            if (disc >= 0.0) {
-                const double root = std::sqrt(disc);
-                const double sig = std::fabs(mid + root - d) <= std::fabs(mid - root - d) ? mid + root : mid - root;
-                s = 2.0 * sig;
-                t = sig * sig;
-            } else {
-                s = p + d;
-                t = p * d - q * r;
-            }
+            const double root = std::sqrt(-disc);
+            wr[hi - 1] = wr[hi] = mid;
+            wi[hi - 1] = root;
+            wi[hi] = -root;
         }
-        ++its;
-        // first column of (A - s1 I)(A - s2 I) = A^2 - s A + t I (rows l .. l+2)
-        double v[3];
-        v[0] = a(l, l) * a(l, l) + a(l, l + 1) * a(l + 1, l) - s * a(l, l) + t;
-        v[1] = a(l + 1, l) * (a(l, l) + a(l + 1, l + 1) - s);
-        v[2] = a(l + 1, l) * a(l + 2, l + 1);
-        for (int k = l; k < hi; ++k) {
-            const int len = hi - k + 1 < 3 ? hi - k + 1 : 3;
-            if (k > l)
-                for (int i = 0; i < len; ++i) v[i] = a(k + i, k - 1);
-            // reflector I - beta u u^T mapping v onto a multiple of e_1
-            double nv = 0.0;
-            for (int i = 0; i < len; ++i) nv += v[i] * v[i];
-            nv = std::sqrt(nv);
-            if (nv == 0.0) continue;
-            const double alpha = v[0] >= 0.0 ? -nv : nv;
-            double u[3] = {v[0] - alpha, len > 1 ? v[1] : 0.0, len > 2 ? v[2] : 0.0};
-            double uu = 0.0;
-            for (int i = 0; i < len; ++i) uu += u[i] * u[i];
-            if (uu == 0.0) continue;
-            const double beta = 2.0 / uu;
-            // from the left: rows k .. k+len-1, columns from the bulge's column to hi
-            for (int j = (k > l ? k - 1 : l); j <= hi; ++j) {
-                double dot = 0.0;
-                for (int i = 0; i < len; ++i) dot += u[i] * a(k + i, j);
-                dot *= beta;
-                for (int i = 0; i < len; ++i) a(k + i, j) -= dot * u[i];
-            }
-            if (k > l) {  // the reflector zeroed the bulge below a(k, k-1)
-                a(k, k - 1) = alpha;
-                for (int i = 1; i < len; ++i) a(k + i, k - 1) = 0.0;
-            }
-            // from the right: columns k .. k+len-1, rows l .. min(k+3, hi)
-            const int rmax = k + 3 < hi ? k + 3 : hi;
-            for (int i = l; i <= rmax; ++i) {
-                double dot = 0.0;
-                for (int j = 0; j < len; ++j) dot += a(i, k + j) * u[j];
-                dot *= beta;
-                for (int j = 0; j < len; ++j) a(i, k + j) -= dot * u[j];
-            }
-        }
+        hi -= 2;
     }
     return true;
 }

@@ -34,6 +34,15 @@ def test_exports_every_declared_symbol(L):
         assert hasattr(L, n), f"{n} declared in sdbie.h but not exported"
 
 
+def test_header_constants_match_the_binding():
+    from paper_2110_10749_amd import binding as B
+    src = open(HEADER).read()
+    defs = dict(re.findall(r"^#define\s+(SDBIE_[A-Z0-9_]+)\s+(\S+)", src, flags=re.M))
+    assert int(defs["SDBIE_SYM_LAPLACE"]) == B.SYM_LAPLACE and int(defs["SDBIE_SYM_STOKES"]) == B.SYM_STOKES
+    assert defs["SDBIE_SYM_DEFAULT"] == "SDBIE_SYM_LAPLACE" and B.SYM_DEFAULT == B.SYM_LAPLACE
+    assert int(defs["SDBIE_NOALLOC_MAX_NODES"]) == B.NOALLOC_MAX_NODES
+
+
 def test_abi_version_and_default_opts(L):
     from paper_2110_10749_amd import binding
     assert L.sdbie_abi_version() == 4
@@ -95,6 +104,7 @@ def test_invalid_arguments_are_rejected_on_the_host(L):
     d = (ctypes.c_double * 3)()
     assert L.ddm_solve(None, ctypes.byref(prm), U, None, None, None, d, None, None, None) == B.ERR_ARG
     assert L.sdbie_plan_n(None) == -1
+    assert L.sdbie_plan_set_symmetric(None, 1) == B.ERR_ARG
 
 
 def _match(a, b):
@@ -192,6 +202,41 @@ def test_hessenberg_eigenvalues_with_exact_multiplets(L):
     V[:, 0] = v / np.linalg.norm(v)
     for k in range(m):
         w = A @ V[:, k]
+        for _ in range(2):
+            h = V[:, :k + 1].T @ w
+            w -= V[:, :k + 1] @ h
+            Hm[:k + 1, k] += h
+        Hm[k + 1, k] = np.linalg.norm(w)
+        V[:, k + 1] = w / Hm[k + 1, k]
+    got = np.array(B.hessenberg_eigenvalues(Hm[:m, :m]))
+    ref = np.linalg.eigvals(Hm[:m, :m])
+    assert _match(got, ref) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("seed,K,noise", [(0, 1.0, 1e-7), (4, 1e-2, 3e-7), (11, 1e-4, 1e-8)])
+def test_hessenberg_eigenvalues_of_inexact_arnoldi(L, seed, K, noise):
+    # Arnoldi whose products carry a relative error (as with float pair sums in
+    # the local solves): the multiplets of the D-N map split into clusters of
+    # eigenvalues a few ulps to 1e-8 apart, and a double-shift step whose first
+    # column is formed from the sum and product of the shifts cancels to noise
+    # on them (the iteration stalled on these matrices); against LAPACK
+    import numpy as np
+    from paper_2110_10749_amd import binding as B
+    rng = np.random.default_rng(seed)
+    lam = []
+    for n in range(1, 60):
+        lam += [-(n + 1) * (2 * n + 1) / (2 * n * (n + 2) * (2 * n * n + 1)) / K] * (2 * n + 1)
+    lam = np.array(lam[:2000])
+    Q, _ = np.linalg.qr(rng.normal(size=(lam.size, lam.size)))
+    A = (Q * lam) @ Q.T
+    m = 240
+    V = np.zeros((lam.size, m + 1))
+    Hm = np.zeros((m + 1, m))
+    v = rng.normal(size=lam.size)
+    V[:, 0] = v / np.linalg.norm(v)
+    for k in range(m):
+        w = A @ V[:, k]
+        w += noise * np.linalg.norm(w) * rng.normal(size=w.size) / np.sqrt(w.size)
         for _ in range(2):
             h = V[:, :k + 1].T @ w
             w -= V[:, :k + 1] @ h

@@ -7,7 +7,9 @@ checked against the paper's printed Table 1 errors and the closed forms.
 The mixed path (float pairs + double refinement) is held to the same final
 accuracy as the FP64 path.
 """
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -19,6 +21,7 @@ from workloads import exact, fields, surfaces
 pytestmark = pytest.mark.gpu
 
 E = np.array([0.0, 0.0, 1.0])
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -374,9 +377,16 @@ def test_table2_relaxation_exceeds_100_iterations(sd, s16, golden, K):
     # Table 2: with theta = c kappa (c = 0.5, 0.75) the relaxed D-N iteration
     # needs more than 100 iterations to reach the residual 1e-9 of eq.
     # (DDM_residual) for kappa = 1e-2 and 1e-4 (the iteration matrix has most of
-    # its eigenvalues near 1 - theta); D-N by GMRES converges in a few
+    # its eigenvalues near 1 - theta).  D-N by GMRES converges; its iteration
+    # count is pinned to the oracle's matrix-free solve of the same problem
+    # (tests/golden/oracle_dn_gmres_h16.json: 10 and 42, against the paper's
+    # printed 7 and 8): with exact interface products within one iteration
+    # (rounding moves the step at which the residual crosses 1e-9), with the
+    # default inexact products within three (one correction cycle)
     S, geo, ops, plan = s16
     cap = golden["table2_dn_sa_exceeds"]["iterations"]
+    with open(os.path.join(GOLDEN_DIR, "oracle_dn_gmres_h16.json")) as f:
+        ref = json.load(f)["iterations"][f"{K:g}"]
     fx = dev(exact.jt_viscous_traction(S.x, E, K=K))
     for c in (0.5, 0.75):
         opts = dict(outer="sa", theta=c * K, tol_gmres=1e-9, tol_ddm=1e-9, maxit_ddm=cap)
@@ -384,6 +394,8 @@ def test_table2_relaxation_exceeds_100_iterations(sd, s16, golden, K):
         print(f"K={K:g} theta={c}K: relaxation after {info['ddm_iters']} iterations: residual {info['ddm_res']:.2e}",
               flush=True)
         assert not info["converged"] and info["ddm_iters"] == cap and info["ddm_res"] > 1e-9
-    p, u, D, info = sd.ddm_solve(plan, 1.0, K, 0.0, E, fx, opts=dict(outer="gmres", tol_gmres=1e-9, tol_ddm=1e-9))
-    print(f"K={K:g}: D-N by GMRES {info['ddm_iters']} iterations", flush=True)
-    assert info["converged"] and info["ddm_iters"] <= 30
+    for relax, slack in ((0, 1), (1, 3)):
+        p, u, D, info = sd.ddm_solve(plan, 1.0, K, 0.0, E, fx,
+                                     opts=dict(outer="gmres", tol_gmres=1e-9, tol_ddm=1e-9, relax_outer=relax))
+        print(f"K={K:g}: D-N by GMRES (relax_outer {relax}) {info['ddm_iters']} iterations, oracle {ref}", flush=True)
+        assert info["converged"] and abs(info["ddm_iters"] - ref) <= slack

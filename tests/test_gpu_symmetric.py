@@ -8,8 +8,9 @@ molecule at h = 1/32 (many far tile pairs): within 1e-12 (FP64) and 3e-6
 (float pairs, raw double layer within its coordinate-rounding bound) of the
 oracle on every row, and within 1e-13 / 2e-6 of the one-direction GPU sums
 (the same pairs summed in another order).  A mixed and an FP64 coupled solve
-with the symmetric far field land on the one-direction solve's drag (1e-10)
-and fields (1e-8).
+with the symmetric far field for the Laplace passes only (the default of a new
+plan) and for both families land on the one-direction solve's drag (1e-10) and
+fields (1e-8).
 """
 import numpy as np
 import pytest
@@ -39,6 +40,7 @@ def test_symmetric_layers_against_oracle_and_one_direction(sd, kind):
     delta = 3.0 / 32
     geo = O.Geometry(S.x, S.n, S.w, delta)
     plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), delta)
+    assert sd.SYM_DEFAULT == sd.SYM_LAPLACE
     q = fields.random_scalar(S.N, 61)
     u = fields.random_vector(S.N, 62)
     mu = 1.3
@@ -71,13 +73,14 @@ def test_symmetric_far_field_in_the_coupled_solve(sd, prec):
     plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), 3.0 / 32)
     E = [0.0, 0.0, 1.0]
     out = {}
-    for sym in (False, True):
+    for sym in (0, sd.SYM_LAPLACE, sd.SYM_LAPLACE | sd.SYM_STOKES):
         plan.set_symmetric(sym)
         p, u, D, info = sd.ddm_solve(plan, 1.0, 1e-2, 1.0, E, None, opts=dict(prec=prec, tol_gmres=1e-12,
                                                                               tol_ddm=1e-11))
-        print(prec, "symmetric" if sym else "one-direction", D[2], info, flush=True)
+        print(prec, f"symmetric families {sym}", D[2], info, flush=True)
         assert info["converged"]
         out[sym] = (p.cpu().numpy(), u.cpu().numpy(), D[2])
-    assert abs(out[True][2] - out[False][2]) < 1e-10 * abs(out[False][2])
-    assert relerr(out[True][0], out[False][0]) < 1e-8 and relerr(out[True][1], out[False][1]) < 1e-8
+    for sym in out:
+        assert abs(out[sym][2] - out[0][2]) < 1e-10 * abs(out[0][2])
+        assert relerr(out[sym][0], out[0][0]) < 1e-8 and relerr(out[sym][1], out[0][1]) < 1e-8
     plan.close()
