@@ -142,6 +142,36 @@ def measured_traffic(kernel_name: str, n: int):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
+def time_passes(sd, plan, S, dev) -> int:
+    """Per-pass kernel times (HIP events of the library) of every layer kind,
+    precision and symmetric-family setting, one JSON line each."""
+    import torch
+    from workloads import fields
+    q = dev(fields.random_scalar(S.N, 1))
+    u = dev(fields.random_vector(S.N, 2))
+    for prec in ("mixed", "fp64"):
+        for mask in (0, sd.SYM_LAPLACE | sd.SYM_STOKES):
+            plan.set_symmetric(mask)
+            for fam, layer in (("laplace", "sl"), ("laplace", "dl_sub"), ("stokes", "sl"), ("stokes", "dl_sub")):
+                if fam == "laplace":
+                    f = lambda: sd.laplace_layer_apply(plan, layer, q, prec=prec)
+                else:
+                    f = lambda: sd.stokes_layer_apply(plan, 1.0, layer, u, prec=prec)
+                f()
+                torch.cuda.synchronize()
+                sd.profile_enable(True)
+                for _ in range(5):
+                    f()
+                torch.cuda.synchronize()
+                st = sd.profile_read()
+                sd.profile_enable(False)
+                k = max((x for x in st if x["pairs"] > 0), key=lambda x: x["ms"])
+                print(json.dumps({"pass": f"{fam} {layer}", "prec": prec, "symmetric": bool(mask),
+                                  "kernel": k["name"], "ms_per_launch": k["ms"] / k["launches"]}), flush=True)
+    plan.set_symmetric(sd.SYM_DEFAULT)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +183,10 @@ def main() -> int:
                          "at h=1/128 (N=351866), K=1e-3, U seeded on the unit sphere")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--passes", action="store_true",
+                    help="only time the single layer passes of the workload's surface (Laplace and Stokes single "
+                         "and subtracted double layers of seeded densities, float and double pairs, one-direction "
+                         "and target-source symmetric far field), 5 launches each, and exit")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates the HBM "
                          "byte counters of a profiler) and exit")
@@ -211,6 +245,8 @@ def main() -> int:
         stage_ms.append(1e3 * (time.perf_counter() - t0))
         plan.close()
     plan = sd.Plan(xd, nd, wd, delta)
+    if args.passes:
+        return time_passes(sd, plan, S, dev)
     opts_mixed = dict(prec="mixed", outer="gmres", tol_gmres=1e-10, tol_ddm=1e-8)
     opts_fp64 = dict(prec="fp64", outer="gmres", tol_gmres=1e-10, tol_ddm=1e-8)
     flow = lambda D: float(np.dot(D, E))

@@ -104,6 +104,11 @@ struct Ctx {
     // loose32: every pass of the local solves (right-hand sides included) in float pairs
     double tol_local = 0.0;
     bool loose32 = false;
+    // estimate_only: the relaxed GMRES of a local solve ends on its own
+    // residual estimate, without the double-pair true residual (set for the
+    // solves whose results only enter an interface product, when the final
+    // solves and the true interface residual certify the answer)
+    bool estimate_only = false;
     // index of the Krylov basis vector the operator is being applied to (-1: a residual)
     int krylov_index = -1;
     // deflation of the Stokes local solves (opts.recycle): rc_cur is set around
