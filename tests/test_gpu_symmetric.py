@@ -41,6 +41,8 @@ def test_symmetric_layers_against_oracle_and_one_direction(sd, kind):
     geo = O.Geometry(S.x, S.n, S.w, delta)
     plan = sd.Plan(dev(S.x), dev(S.n), dev(S.w), delta)
     assert sd.SYM_DEFAULT == sd.SYM_LAPLACE
+    with pytest.raises(sd.SdbieError):
+        plan.set_symmetric(4)  # no such pass family
     q = fields.random_scalar(S.N, 61)
     u = fields.random_vector(S.N, 62)
     mu = 1.3
