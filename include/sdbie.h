@@ -150,9 +150,11 @@ void sdbie_default_opts(sdbie_opts* o);
  * invalid).  Roughly (120 max_restart + 1185 + 96 S) n bytes plus
  * (n/256)^2 * 3471, with S the source splits of a pair pass (a multiple of 8
  * up to 64: 64 at n = 4096, 16 at n = 68166, 8 from n = 131072 on); the
- * quadratic term is the tile masks and the partial sums of the symmetric far
- * field (sdbie_plan_set_symmetric): 0.84 GB at n = 68166, 9.4 GB at n = 351866
- * with max_restart = 50. */
+ * quadratic term is the tile masks and the work lists and partial sums of the
+ * symmetric far field (sdbie_plan_set_symmetric): 0.84 GB at n = 68166,
+ * 9.4 GB at n = 351866 with max_restart = 50.  Above n = 524288 a plan holds
+ * no symmetric lists (the quadratic term drops to the masks, (n/256)^2 * 2)
+ * and runs every pass one direction at a time. */
 size_t sdbie_workspace_bytes(int64_t n, int max_restart);
 
 /* Stage a surface: spatial (Morton) ordering, double and float copies of the
@@ -175,7 +177,9 @@ int64_t sdbie_plan_n(sdbie_plan plan);
  * excepted) a pass of a selected family evaluates each tile pair whose node
  * pairs all lie beyond the smoothing cutoff once, adding its contributions to
  * the targets of both tiles; near tile pairs stay one pass per direction.
- * Same sums up to rounding.  0: every ordered pair in its own pass.  The
+ * Same sums up to rounding.  0: every ordered pair in its own pass.  Plans
+ * of more than 524288 nodes have no room for the symmetric lists and keep
+ * every pass one-directional whatever the mask.  The
  * default, SDBIE_SYM_DEFAULT, selects the Laplace passes only: on gfx950 the
  * symmetric Laplace passes are faster than the one-direction ones, the
  * symmetric Stokes passes slower (their reverse sums move through cross-lane

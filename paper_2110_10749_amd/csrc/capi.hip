@@ -31,7 +31,11 @@ struct Layout {
 };
 
 // bounds of the symmetric far-field lists: at most T (T - 1) / 2 far tile
-// pairs, and at most pairs / kSymChunk + T blocks
+// pairs, and at most pairs / kSymChunk + T blocks.  The lists and partial
+// slots grow as T^2 (about 3469 bytes per tile pair), so plans of more than
+// kSymMaxTiles tiles hold none and run every pass one direction at a time.
+constexpr int64_t kSymMaxTiles = 2048;  // 524288 nodes: 14.6 GB of lists and slots
+bool sym_fits(int64_t nt) { return nt <= kSymMaxTiles; }
 int64_t sym_max_pairs(int64_t nt) { return nt * (nt - 1) / 2; }
 int64_t sym_max_blocks(int64_t nt) { return sym_max_pairs(nt) / kSymChunk + nt; }
 
@@ -63,7 +67,7 @@ void layout_common(Layout& L, Take& take, int64_t n, int m, int nsplit, int comp
 }
 
 Layout layout(int64_t n, int m) {
-    Layout L;
+    Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -78,14 +82,16 @@ Layout layout(int64_t n, int m) {
     L.image_out = take((size_t)(m + 1) * kImageStride * n * d);
     L.basis_rc = take((size_t)(m + 1) * 3 * n * d);
     const int64_t nt = (n + kTile - 1) / kTile;
-    for (int k = 0; k < 2; ++k) {
-        L.sym_items[k] = take((size_t)sym_max_pairs(nt) * 3 * sizeof(int32_t));
-        L.sym_blocks[k] = take((size_t)sym_max_blocks(nt) * 2 * sizeof(int32_t));
-        L.sym_fwd_start[k] = take((size_t)(nt + 1) * sizeof(int32_t));
-        L.sym_rev_start[k] = take((size_t)(nt + 1) * sizeof(int32_t));
+    if (sym_fits(nt)) {
+        for (int k = 0; k < 2; ++k) {
+            L.sym_items[k] = take((size_t)sym_max_pairs(nt) * 3 * sizeof(int32_t));
+            L.sym_blocks[k] = take((size_t)sym_max_blocks(nt) * 2 * sizeof(int32_t));
+            L.sym_fwd_start[k] = take((size_t)(nt + 1) * sizeof(int32_t));
+            L.sym_rev_start[k] = take((size_t)(nt + 1) * sizeof(int32_t));
+        }
+        L.sym_fwd = take((size_t)sym_max_blocks(nt) * 3 * kTile * d);
+        L.sym_rev = take((size_t)sym_max_pairs(nt) * 3 * kTile * d);  // double partials for the FP64 passes
     }
-    L.sym_fwd = take((size_t)sym_max_blocks(nt) * 3 * kTile * d);
-    L.sym_rev = take((size_t)sym_max_pairs(nt) * 3 * kTile * d);  // double partials for the FP64 passes
     L.total = off;
     return L;
 }
@@ -213,6 +219,7 @@ void carve_workspace(Plan& P, void* ws) {
     P.basis_out = reinterpret_cast<double*>(b + L.basis_out);
     P.image_out = reinterpret_cast<double*>(b + L.image_out);
     P.basis_rc = reinterpret_cast<double*>(b + L.basis_rc);
+    if (!sym_fits((P.n + kTile - 1) / kTile)) return;  // no symmetric lists: every pass one direction
     for (int k = 0; k < 2; ++k) {
         P.sym_items[k] = reinterpret_cast<int32_t*>(b + L.sym_items[k]);
         P.sym_blocks[k] = reinterpret_cast<int32_t*>(b + L.sym_blocks[k]);

@@ -30,10 +30,12 @@ def make_plan(sd, x, n, w, delta):
     return sd.Plan(dev(x), dev(n), dev(w), delta)
 
 
-def check_all_layers(sd, x, n, w, delta, seed, mu=1.3, targets=None, precs=("fp64", "mixed")):
+def check_all_layers(sd, x, n, w, delta, seed, mu=1.3, targets=None, precs=("fp64", "mixed"), symmetric=None):
     N = w.shape[0]
     geo = O.Geometry(x, n, w, delta)
     plan = make_plan(sd, x, n, w, delta)
+    if symmetric is not None:
+        plan.set_symmetric(symmetric)
     q = fields.random_scalar(N, seed)
     u = fields.random_vector(N, seed + 1)
     out = {}

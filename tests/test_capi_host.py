@@ -63,12 +63,16 @@ def test_workspace_bytes(L):
     assert binding.workspace_bytes(100, 1000) > 0 and binding.workspace_bytes(100, 1001) == 0
 
 
-@pytest.mark.parametrize("n,m,splits", [(4096, 50, 64), (68166, 50, 16), (68166, 1000, 16), (351866, 50, 8)])
+@pytest.mark.parametrize("n,m,splits", [(4096, 50, 64), (68166, 50, 16), (68166, 1000, 16), (351866, 50, 8),
+                                         (524288, 50, 8), (524289, 50, 8), (1 << 23, 50, 8)])
 def test_workspace_formula_in_header(L, n, m, splits):
-    # the header's estimate (120 m + 1185 + 96 S) n + (n/256)^2 * 3471, within 1%
+    # the header's estimate (120 m + 1185 + 96 S) n + (n/256)^2 * q, q = 3471
+    # up to 524288 nodes (masks and symmetric lists), 2 above (masks only),
+    # within 1%
     from paper_2110_10749_amd import binding
     nt = (n + 255) // 256
-    est = (120 * m + 1185 + 96 * splits) * n + 3471 * nt * nt
+    q = 3471 if n <= 524288 else 2
+    est = (120 * m + 1185 + 96 * splits) * n + q * nt * nt
     assert abs(est / binding.workspace_bytes(n, m) - 1.0) < 0.01
 
 

@@ -294,3 +294,18 @@ def test_large_perturbed_sphere_h128(sd):
         assert e1 < 1e-8 and e2 < 1e-8
     assert rel(res["mixed"][0], res["fp64"][0]) < 1e-8
     assert rel(res["mixed"][1], res["fp64"][1]) < 1e-8
+
+
+def test_layers_beyond_the_symmetric_limit(sd):
+    # a plan of more than 524288 nodes holds no symmetric far-field lists (they
+    # grow as the square of the tile count) and runs every pass one direction
+    # at a time whatever the mask: 600000 seeded points on the unit sphere,
+    # every layer against the oracle on 24 sampled rows
+    N = 600000
+    rng = np.random.default_rng(71)
+    x = rng.normal(size=(3, N))
+    x /= np.linalg.norm(x, axis=0)
+    w = np.full(N, 4.0 * math.pi / N)
+    delta = 3.0 * math.sqrt(4.0 * math.pi / N)
+    t = np.sort(rng.choice(N, size=24, replace=False))
+    check_all_layers(sd, x, x.copy(), w, delta, seed=72, targets=t, symmetric=sd.SYM_LAPLACE | sd.SYM_STOKES)
