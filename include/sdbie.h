@@ -278,15 +278,17 @@ int ddm_adjoint(sdbie_plan plan, const sdbie_params* prm, const double U[3], con
  * eig_im: host double[k] (1 <= k <= m) receive the k Ritz values of largest
  * modulus in decreasing modulus (NaN past the steps taken when the Krylov
  * space becomes invariant; info->ddm_iters = steps taken).  Returns
- * NOT_CONVERGED if a local solve missed its tolerance. */
+ * NOT_CONVERGED if a local solve missed its tolerance or the QR iteration
+ * stalled (then the eigenvalues it did not reach are NaN, listed last). */
 int ddm_dn_spectrum(sdbie_plan plan, const sdbie_params* prm, const double* v0, int m, int k, double* eig_re,
                     double* eig_im, const sdbie_opts* opts, sdbie_info* info, void* stream);
 
 /* Eigenvalues of an upper Hessenberg matrix H (host, n x n, row-major; the
  * entries below the subdiagonal are ignored) by the Francis double-shift QR
  * iteration, the host step of ddm_dn_spectrum: eig_re, eig_im (host
- * double[n]) in no particular order, complex pairs adjacent.  ERR_DEVICE if
- * the iteration stalls. */
+ * double[n]) in no particular order, complex pairs adjacent.  NOT_CONVERGED
+ * if 30 max(10, n) QR steps pass without a deflation (the eigenvalues not
+ * reached are NaN); ERR_ARG for n < 1 or a null pointer. */
 int sdbie_hessenberg_eigenvalues(int n, const double* H, double* eig_re, double* eig_im);
 
 /* Kernel timing (diagnostics).  While enabled, every pair-sum kernel launch

@@ -367,5 +367,5 @@ def hessenberg_eigenvalues(H):
     n = len(H)
     flat = (ctypes.c_double * (n * n))(*[float(H[i][j]) for i in range(n) for j in range(n)])
     re, im = (ctypes.c_double * n)(), (ctypes.c_double * n)()
-    _check(lib().sdbie_hessenberg_eigenvalues(n, flat, re, im))
+    _check(lib().sdbie_hessenberg_eigenvalues(n, flat, re, im), allow_not_converged=False)
     return [complex(re[i], im[i]) for i in range(n)]

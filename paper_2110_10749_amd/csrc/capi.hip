@@ -509,12 +509,13 @@ int ddm_dn_spectrum(sdbie_plan plan, const sdbie_params* prm, const double* v0, 
         std::vector<double> A((size_t)used * used), wr(used), wi(used);
         for (int i = 0; i < used; ++i)
             for (int j = 0; j < used; ++j) A[(size_t)i * used + j] = H[(size_t)i * m + j];
-        if (!hessenberg_eigenvalues(used, A.data(), wr.data(), wi.data()))
-            fail(SDBIE_ERR_DEVICE, "the Hessenberg QR iteration did not converge");
+        const bool qr_ok = hessenberg_eigenvalues(used, A.data(), wr.data(), wi.data());
+        if (!qr_ok) g_last_error = "the Hessenberg QR iteration did not converge";
+        // decreasing modulus; eigenvalues the QR iteration did not reach (NaN) last
+        auto mod = [&](int i) { return std::isnan(wr[i]) ? -1.0 : std::hypot(wr[i], wi[i]); };
         std::vector<int> order(used);
         for (int i = 0; i < used; ++i) order[i] = i;
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int a, int b) { return std::hypot(wr[a], wi[a]) > std::hypot(wr[b], wi[b]); });
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return mod(a) > mod(b); });
         for (int i = 0; i < k; ++i) {
             eig_re[i] = i < used ? wr[order[i]] : NAN;
             eig_im[i] = i < used ? wi[order[i]] : NAN;
@@ -522,7 +523,7 @@ int ddm_dn_spectrum(sdbie_plan plan, const sdbie_params* prm, const double* v0, 
         c.info.ddm_iters = used;
         c.finish();
         if (info) *info = c.info;
-        return c.converged ? SDBIE_OK : SDBIE_NOT_CONVERGED;
+        return c.converged && qr_ok ? SDBIE_OK : SDBIE_NOT_CONVERGED;
     });
 }
 
@@ -532,8 +533,10 @@ int sdbie_hessenberg_eigenvalues(int n, const double* H, double* eig_re, double*
         std::vector<double> A(H, H + (size_t)n * n);
         for (int i = 2; i < n; ++i)
             for (int j = 0; j < i - 1; ++j) A[(size_t)i * n + j] = 0.0;  // only the Hessenberg part is read
-        if (!hessenberg_eigenvalues(n, A.data(), eig_re, eig_im))
-            fail(SDBIE_ERR_DEVICE, "the Hessenberg QR iteration did not converge");
+        if (!hessenberg_eigenvalues(n, A.data(), eig_re, eig_im)) {
+            g_last_error = "the Hessenberg QR iteration did not converge";
+            return SDBIE_NOT_CONVERGED;
+        }
         return SDBIE_OK;
     });
 }

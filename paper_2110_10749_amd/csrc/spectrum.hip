@@ -66,7 +66,7 @@ static void double_shift(double h11, double h12, double h21, double h22, double 
 // consecutive subdiagonal entries are small enough; ad hoc shifts every 10
 // steps without deflation break cycles; 1x1 and 2x2 blocks give their
 // eigenvalues in closed form.  Returns false if 30 max(10, n) steps pass
-// without a deflation.
+// without a deflation; the eigenvalues not reached by then are NaN.
 bool hessenberg_eigenvalues(int n, double* A, double* wr, double* wi) {
     auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
     const double ulp = DBL_EPSILON, tiny = DBL_MIN;
@@ -95,7 +95,10 @@ bool hessenberg_eigenvalues(int n, double* A, double* wr, double* wi) {
             }
             if (l > 0) a(l, l - 1) = 0.0;
             if (l >= hi - 1) break;  // a 1x1 or 2x2 block has split off
-            if (its >= itmax) return false;
+            if (its >= itmax) {
+                for (int i = 0; i <= hi; ++i) wr[i] = wi[i] = NAN;
+                return false;
+            }
             ++kdefl;
             double sh[4];
             if (kdefl % 20 == 0) {  // ad hoc shift from the top of the window

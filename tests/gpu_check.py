@@ -30,7 +30,8 @@ def make_plan(sd, x, n, w, delta):
     return sd.Plan(dev(x), dev(n), dev(w), delta)
 
 
-def check_all_layers(sd, x, n, w, delta, seed, mu=1.3, targets=None, precs=("fp64", "mixed"), symmetric=None):
+def check_all_layers(sd, x, n, w, delta, seed, mu=1.3, targets=None, precs=("fp64", "mixed"), symmetric=None,
+                     tol32=TOL32):
     N = w.shape[0]
     geo = O.Geometry(x, n, w, delta)
     plan = make_plan(sd, x, n, w, delta)
@@ -48,9 +49,9 @@ def check_all_layers(sd, x, n, w, delta, seed, mu=1.3, targets=None, precs=("fp6
             if targets is not None:
                 gl, gs = gl[targets], gs[:, targets]
             el, es = relerr(gl, ref_l), relerr(gs, ref_s)
-            tol = TOL64 if prec == "fp64" else TOL32
+            tol = TOL64 if prec == "fp64" else tol32
             if prec == "mixed" and name == "dl_raw":
-                tol = max(TOL32, 4 * EPS32 * np.max(np.abs(x)) / delta**2)
+                tol = max(tol32, 4 * EPS32 * np.max(np.abs(x)) / delta**2)
             print(f"N={N} {name:7s} {prec:5s} laplace {el:.2e} stokes {es:.2e}", flush=True)
             assert el < tol, (name, prec, "laplace", el)
             assert es < tol, (name, prec, "stokes", es)
