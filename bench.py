@@ -169,7 +169,7 @@ def time_passes(sd, plan, S, dev) -> int:
     q = dev(fields.random_scalar(S.N, 1))
     u = dev(fields.random_vector(S.N, 2))
     for prec in ("mixed", "fp64"):
-        for mask in (0, sd.SYM_LAPLACE | sd.SYM_STOKES):
+        for mask in (0, sd.SYM_ALL):
             plan.set_symmetric(mask)
             for fam, layer in (("laplace", "sl"), ("laplace", "dl_sub"), ("stokes", "sl"), ("stokes", "dl_sub")):
                 if fam == "laplace":

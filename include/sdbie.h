@@ -171,23 +171,25 @@ int64_t sdbie_plan_n(sdbie_plan plan);
 
 /* Target-source symmetric far field (section "Numerical Results", local
  * problems: the paper's code evaluates each pair of nodes once for both
- * directions).  `families` is a mask of SDBIE_SYM_LAPLACE (the Laplace single
- * and double layer passes) and SDBIE_SYM_STOKES (the Stokes passes): in every
- * later layer sum and solve on the plan (the transposed sums of ddm_adjoint
- * excepted) a pass of a selected family evaluates each tile pair whose node
- * pairs all lie beyond the smoothing cutoff once, adding its contributions to
- * the targets of both tiles; near tile pairs stay one pass per direction.
- * Same sums up to rounding.  0: every ordered pair in its own pass.  Plans
- * of more than 524288 nodes have no room for the symmetric lists and keep
- * every pass one-directional whatever the mask.  The
- * default, SDBIE_SYM_DEFAULT, selects the Laplace passes only: on gfx950 the
- * symmetric Laplace passes are faster than the one-direction ones, the
- * symmetric Stokes passes slower (their reverse sums move through cross-lane
- * operations that issue at half rate).  ERR_ARG for a null plan or unknown
- * bits. */
+ * directions).  `families` is a mask of SDBIE_SYM_LAPLACE and SDBIE_SYM_STOKES
+ * (the Laplace or Stokes passes with float pairs) and SDBIE_SYM_LAPLACE_F64
+ * and SDBIE_SYM_STOKES_F64 (the same with double pairs): in every later layer
+ * sum and solve on the plan (the transposed sums of ddm_adjoint excepted) a
+ * pass of a selected kind evaluates each tile pair whose node pairs all lie
+ * beyond the smoothing cutoff once, adding its contributions to the targets
+ * of both tiles; near tile pairs stay one pass per direction.  Same sums up to
+ * rounding.  0: every ordered pair in its own pass.  Plans of more than 524288
+ * nodes have no room for the symmetric lists and keep every pass
+ * one-directional whatever the mask.  The default, SDBIE_SYM_DEFAULT, selects
+ * the kinds that are faster symmetric on gfx950: all but the double Stokes
+ * passes (those spend more on moving a double record between lanes than the
+ * shared geometry saves).  ERR_ARG for a null plan or unknown bits. */
 #define SDBIE_SYM_LAPLACE 1
 #define SDBIE_SYM_STOKES 2
-#define SDBIE_SYM_DEFAULT SDBIE_SYM_LAPLACE
+#define SDBIE_SYM_LAPLACE_F64 4
+#define SDBIE_SYM_STOKES_F64 8
+#define SDBIE_SYM_ALL 15
+#define SDBIE_SYM_DEFAULT (SDBIE_SYM_LAPLACE | SDBIE_SYM_STOKES | SDBIE_SYM_LAPLACE_F64)
 int sdbie_plan_set_symmetric(sdbie_plan plan, int families);
 
 /* out = layer sum of `dens` (device, [n] for Laplace, [3][n] for Stokes, in

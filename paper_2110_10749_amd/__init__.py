@@ -5,7 +5,8 @@ this package is its ctypes binding.  See `binding` for the call surface.
 """
 from .binding import (  # noqa: F401
     ddm_adjoint, ddm_dn_spectrum, hessenberg_eigenvalues,
-    DL_RAW, DL_SUB, FP64, MIXED, SL, SYM_DEFAULT, SYM_LAPLACE, SYM_STOKES, Plan, SdbieError, darcy_solve, ddm_solve, default_opts,
+    DL_RAW, DL_SUB, FP64, MIXED, SL, SYM_ALL, SYM_DEFAULT, SYM_LAPLACE, SYM_LAPLACE_F64, SYM_STOKES, SYM_STOKES_F64,
+    Plan, SdbieError, darcy_solve, ddm_solve, default_opts,
     laplace_layer_apply, lib, profile_enable, profile_read, stokes_layer_apply, stokes_layer_apply_noalloc,
     stokes_solve,
     workspace_bytes,

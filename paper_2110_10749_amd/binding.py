@@ -185,10 +185,13 @@ def workspace_bytes(n: int, max_restart: int = 50) -> int:
     return int(lib().sdbie_workspace_bytes(n, max_restart))
 
 
-# pass families of sdbie_plan_set_symmetric (SDBIE_SYM_*)
+# pass kinds of sdbie_plan_set_symmetric (SDBIE_SYM_*): float-pair and double-pair passes
 SYM_LAPLACE = 1
 SYM_STOKES = 2
-SYM_DEFAULT = SYM_LAPLACE
+SYM_LAPLACE_F64 = 4
+SYM_STOKES_F64 = 8
+SYM_ALL = 15
+SYM_DEFAULT = SYM_LAPLACE | SYM_STOKES | SYM_LAPLACE_F64
 
 
 class Plan:
@@ -224,16 +227,17 @@ class Plan:
     def handle(self):
         return self._h
 
-    def set_symmetric(self, families=SYM_LAPLACE | SYM_STOKES) -> None:
-        """Evaluate the far tile pairs of the selected pass families once for
-        both directions (sdbie_plan_set_symmetric).  ``families``: a mask of
-        SYM_LAPLACE and SYM_STOKES; True means both, False neither.  A new plan
-        starts at SYM_DEFAULT."""
-        if families is True:
-            families = SYM_LAPLACE | SYM_STOKES
-        elif families is False:
-            families = 0
-        _check(lib().sdbie_plan_set_symmetric(self._h, int(families)))
+    def set_symmetric(self, kinds=SYM_ALL) -> None:
+        """Evaluate the far tile pairs of the selected pass kinds once for both
+        directions (sdbie_plan_set_symmetric).  ``kinds``: a mask of
+        SYM_LAPLACE, SYM_STOKES (float pairs), SYM_LAPLACE_F64, SYM_STOKES_F64
+        (double pairs); True means all, False none.  A new plan starts at
+        SYM_DEFAULT."""
+        if kinds is True:
+            kinds = SYM_ALL
+        elif kinds is False:
+            kinds = 0
+        _check(lib().sdbie_plan_set_symmetric(self._h, int(kinds)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -359,7 +359,7 @@ int64_t sdbie_plan_n(sdbie_plan plan) { return plan ? reinterpret_cast<Plan*>(pl
 int sdbie_plan_set_symmetric(sdbie_plan plan, int families) {
     return guarded([&]() -> int {
         Plan& P = plan_of(plan);
-        if (families & ~(SDBIE_SYM_LAPLACE | SDBIE_SYM_STOKES)) fail(SDBIE_ERR_ARG, "unknown pass family bits");
+        if (families & ~SDBIE_SYM_ALL) fail(SDBIE_ERR_ARG, "unknown pass kind bits");
         P.symmetric = families;
         return SDBIE_OK;
     });

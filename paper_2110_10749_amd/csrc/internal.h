@@ -141,7 +141,7 @@ struct Plan {
     double* host_pinned = nullptr;  // not used (host buffers are plain)
     // (target, source) pairs of real nodes in the near tile pairs (double, float masks)
     double near_pairs64 = 0.0, near_pairs32 = 0.0;
-    // target-source symmetric far field (for the pass families whose
+    // target-source symmetric far field (for the pass kinds whose
     // SDBIE_SYM_* bit is set in `symmetric`): per
     // precision (index 0 double, 1 float) the far tile pairs {a < b} numbered
     // in column order (pair p owns a reverse slot), the work items (a, b, p) in

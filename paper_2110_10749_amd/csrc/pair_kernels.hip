@@ -981,27 +981,70 @@ __global__ __launch_bounds__(kTPB) void pass_pairs_wide(KArgs a) {
 //   out = tw * sum + base_scale * base + comp_scale * comp[0] * (1 or n_i) + add
 // out may alias base when perm is null (each lane reads its own elements before
 // writing them).
+// Epilogues run 32 targets per block with 8 threads each: thread group g adds
+// the partial slots g, g + 8, g + 16, ... of its target, and the 8 group sums
+// are added in group order (a fixed order: results are bitwise reproducible).
+// One thread per target left one block per CU and the slot loads
+// latency-bound.
+constexpr int kEpiTargets = 32, kEpiGroups = 8, kEpiThreads = kEpiTargets * kEpiGroups;
+
+// the group sums of v[0..C) for the block's targets, added in group order
+// into the g == 0 threads' v (the other threads' v are left as they are)
 template <int C>
-__global__ void epilogue(int64_t n, int nslots, const double* __restrict__ partial,
-                         const double* __restrict__ tw,
-                         const double* base, double base_scale,
-                         const double* __restrict__ comp, double comp_scale,
-                         const double* __restrict__ nrm, double add0, double add1, double add2,
-                         double* out, const int32_t* __restrict__ perm) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__device__ __forceinline__ void epi_combine(double (&v)[C], int g, int jj) {
+    __shared__ double red[kEpiGroups][C][kEpiTargets];
+#pragma unroll
+    for (int c = 0; c < C; ++c) red[g][c][jj] = v[c];
+    __syncthreads();
+    if (g != 0) return;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < kEpiGroups; ++k) s += red[k][c][jj];
+        v[c] = s;
+    }
+}
+
+// the terms a pass adds to its pair sums v (target weight, base vector,
+// completion, constant) and the store in the caller's node order
+template <int C>
+__device__ __forceinline__ void epi_finish(int64_t n, int64_t i, const double (&v)[C],
+                                           const double* __restrict__ tw, const double* base, double base_scale,
+                                           const double* __restrict__ comp, double comp_scale,
+                                           const double* __restrict__ nrm, double add0, double add1, double add2,
+                                           double* out, const int32_t* __restrict__ perm) {
     const double cs = comp ? comp_scale * comp[0] : 0.0;
     const int64_t o = perm ? (int64_t)perm[i] : i;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        double v = 0.0;
-        for (int s = 0; s < nslots; ++s) v += partial[((int64_t)s * C + c) * n + i];
-        if (tw) v *= tw[i];
-        if (base) v += base_scale * base[c * n + i];
-        if (comp) v += cs * (C == 3 ? nrm[c * n + i] : 1.0);
-        v += (c == 0 ? add0 : (c == 1 ? add1 : add2));
-        out[c * n + o] = v;
+        double s = v[c];
+        if (tw) s *= tw[i];
+        if (base) s += base_scale * base[c * n + i];
+        if (comp) s += cs * (C == 3 ? nrm[c * n + i] : 1.0);
+        s += (c == 0 ? add0 : (c == 1 ? add1 : add2));
+        out[c * n + o] = s;
     }
+}
+
+template <int C>
+__global__ __launch_bounds__(kEpiThreads) void epilogue(int64_t n, int nslots, const double* __restrict__ partial,
+                                                        const double* __restrict__ tw, const double* base,
+                                                        double base_scale, const double* __restrict__ comp,
+                                                        double comp_scale, const double* __restrict__ nrm,
+                                                        double add0, double add1, double add2, double* out,
+                                                        const int32_t* __restrict__ perm) {
+    const int g = threadIdx.x / kEpiTargets, jj = threadIdx.x % kEpiTargets;
+    const int64_t i = (int64_t)blockIdx.x * kEpiTargets + jj;
+    double v[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) v[c] = 0.0;
+    if (i < n)
+        for (int sl = g; sl < nslots; sl += kEpiGroups)
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] += partial[((int64_t)sl * C + c) * n + i];
+    epi_combine<C>(v, g, jj);
+    if (g == 0 && i < n) epi_finish<C>(n, i, v, tw, base, base_scale, comp, comp_scale, nrm, add0, add1, add2, out, perm);
 }
 
 // --------------------------------------------------------------------------
@@ -1011,10 +1054,13 @@ __global__ void epilogue(int64_t n, int nslots, const double* __restrict__ parti
 // algebra; the paper's CPU code halves its pair work this way.  Here each far
 // tile pair {a, b} (a < b, every pair beyond the cutoff) is evaluated once:
 // every lane of a block holds one target of tile a and, in turn, one source
-// of tile b.  Within a wave the sources move across the 16 lanes of each row
-// by DPP row rotations, so at every step each lane evaluates one pair, adds
-// the forward contribution to its own target and hands the reverse one back
-// to the source's lane through the inverse rotation.  A wave meets its 64
+// of tile b.  Within a wave the sources rotate across the 16 lanes of each
+// row: at step K lane l meets the source of lane (l - K) mod 16, its
+// coordinates taken by a DPP row rotation and its other fields read from the
+// tile staged in LDS at that index (SymSrc), so at every step each lane
+// evaluates one pair, adds the forward contribution to its own target and
+// hands the reverse one back to the source's lane through the inverse
+// rotation.  A wave meets its 64
 // targets with a quarter of the 256 sources per phase (4 row rotations of 16
 // steps); the quarters' reverse accumulators pass between the waves in LDS.
 // Forward sums of the target tile go to one slot per block, reverse sums of
@@ -1048,6 +1094,24 @@ __device__ __forceinline__ double rot(double v) {
     }
 }
 
+// The source record a lane meets at step K of a row rotation: the record of
+// lane (l - K) mod 16 of its 16-lane row.  Fields whose bit is set in DPP
+// come from the lane's own record by a DPP rotation (a VALU operand, issued
+// at half rate); the others are read from the tile staged in LDS at the
+// rotated index (the LDS pipe, not the VALU).  lds: field f of source j at
+// lds[f * kTile + j]; jb: first source of the lane's row; l16: lane in row.
+template <typename T, int R, unsigned DPP>
+struct SymSrc {
+    const T* lds;
+    int jb, l16;
+    T own[R];
+    template <int K, int F>
+    __device__ __forceinline__ T get() const {
+        if constexpr ((DPP >> F) & 1u) return rot<K>(own[F]);
+        else return lds[F * kTile + jb + ((l16 - K) & 15)];
+    }
+};
+
 // One step of the symmetric Laplace far field: the lane's target t against
 // the source of the lane K places back in its row (its record read through
 // rot<K>).  Forward (into acc, target t): c_dl w_s (q_s - SUB q_t)(D.n_s) / r^3
@@ -1060,17 +1124,20 @@ struct SymLaplace {
     static constexpr int C = 1, R = Op::R;
     static constexpr int kFamilyBit = SDBIE_SYM_LAPLACE;
     static constexpr int Q = Op::Q, NX = Op::NX, NY = Op::NY, NZ = Op::NZ, G = Op::G;
-    template <int K>
-    __device__ __forceinline__ static void step(const T (&tr)[R], const T (&sr)[R], T (&acc)[C], T (&racc)[C]) {
-        const T dx = tr[0] - rot<K>(sr[0]), dy = tr[1] - rot<K>(sr[1]), dz = tr[2] - rot<K>(sr[2]);
+    template <int K, class Src>
+    __device__ __forceinline__ static void step(const T (&tr)[R], const Src& sr, T (&acc)[C], T (&racc)[C]) {
+        const T dx = tr[0] - sr.template get<K, 0>();
+        const T dy = tr[1] - sr.template get<K, 1>();
+        const T dz = tr[2] - sr.template get<K, 2>();
         const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const T ir = rsq_pos(r2);
         T f = T(0), rv = T(0);
         if constexpr (DL) {
             const T k2 = ir * ir * ir;
-            const T dns = fma(dx, rot<K>(sr[NX]), fma(dy, rot<K>(sr[NY]), dz * rot<K>(sr[NZ])));
+            const T dns =
+                fma(dx, sr.template get<K, NX>(), fma(dy, sr.template get<K, NY>(), dz * sr.template get<K, NZ>()));
             const T dnt = fma(dx, tr[NX], fma(dy, tr[NY], dz * tr[NZ]));
-            const T qs = rot<K>(sr[Q]);
+            const T qs = sr.template get<K, Q>();
             if constexpr (SUB) {
                 const T dq = (qs - tr[Q]) * k2;
                 f = dq * dns;
@@ -1081,7 +1148,7 @@ struct SymLaplace {
             }
         }
         if constexpr (SL) {
-            f = fma(rot<K>(sr[G]), ir, f);
+            f = fma(sr.template get<K, G>(), ir, f);
             rv = fma(tr[G], ir, rv);
         }
         acc[0] += f;
@@ -1102,26 +1169,28 @@ struct SymStokes {
     static constexpr int kFamilyBit = SDBIE_SYM_STOKES;
     static constexpr int NX = Op::NX, NY = Op::NY, NZ = Op::NZ, UX = Op::UX, UY = Op::UY, UZ = Op::UZ;
     static constexpr int FX = Op::FX, FY = Op::FY, FZ = Op::FZ;
-    template <int K>
-    __device__ __forceinline__ static void step(const T (&tr)[R], const T (&sr)[R], T (&acc)[C], T (&racc)[C]) {
-        const T dx = tr[0] - rot<K>(sr[0]), dy = tr[1] - rot<K>(sr[1]), dz = tr[2] - rot<K>(sr[2]);
+    template <int K, class Src>
+    __device__ __forceinline__ static void step(const T (&tr)[R], const Src& sr, T (&acc)[C], T (&racc)[C]) {
+        const T dx = tr[0] - sr.template get<K, 0>();
+        const T dy = tr[1] - sr.template get<K, 1>();
+        const T dz = tr[2] - sr.template get<K, 2>();
         const T r2 = fma(dx, dx, fma(dy, dy, dz * dz));
         const T ir = rsq_pos(r2);
         const T ir2 = ir * ir;
         T ud = T(0), udr = T(0), dns = T(0), dnt = T(0);
         if constexpr (DL) {
-            const T ux = rot<K>(sr[UX]) - (SUB ? tr[UX] : T(0));
-            const T uy = rot<K>(sr[UY]) - (SUB ? tr[UY] : T(0));
-            const T uz = rot<K>(sr[UZ]) - (SUB ? tr[UZ] : T(0));
+            const T ux = sr.template get<K, UX>() - (SUB ? tr[UX] : T(0));
+            const T uy = sr.template get<K, UY>() - (SUB ? tr[UY] : T(0));
+            const T uz = sr.template get<K, UZ>() - (SUB ? tr[UZ] : T(0));
             ud = fma(ux, dx, fma(uy, dy, uz * dz));
             udr = SUB ? ud : -fma(tr[UX], dx, fma(tr[UY], dy, tr[UZ] * dz));
-            dns = fma(dx, rot<K>(sr[NX]), fma(dy, rot<K>(sr[NY]), dz * rot<K>(sr[NZ])));
+            dns = fma(dx, sr.template get<K, NX>(), fma(dy, sr.template get<K, NY>(), dz * sr.template get<K, NZ>()));
             dnt = fma(dx, tr[NX], fma(dy, tr[NY], dz * tr[NZ]));
         }
         T rc[3];
         if constexpr (SL) {
             const T q = ir2 * ir;
-            const T fsx = rot<K>(sr[FX]), fsy = rot<K>(sr[FY]), fsz = rot<K>(sr[FZ]);
+            const T fsx = sr.template get<K, FX>(), fsy = sr.template get<K, FY>(), fsz = sr.template get<K, FZ>();
             const T dfs = fma(dx, fsx, fma(dy, fsy, dz * fsz));
             const T dft = fma(dx, tr[FX], fma(dy, tr[FY], dz * tr[FZ]));
             const T ef = (DL ? fma(ud * dns, ir2, dfs) : dfs) * q;
@@ -1157,7 +1226,8 @@ struct SymOf<StokesOp<T, DL, SL, SUB, SLIP>> { using type = SymStokes<T, DL, SL,
 // the 16 steps of one row rotation, K = 0 .. 15 (compile-time DPP controls)
 template <class Sym, typename T, int K>
 struct SymSteps {
-    __device__ __forceinline__ static void run(const T (&tr)[Sym::R], const T (&sr)[Sym::R], T (&acc)[Sym::C],
+    template <class Src>
+    __device__ __forceinline__ static void run(const T (&tr)[Sym::R], const Src& sr, T (&acc)[Sym::C],
                                                T (&racc)[Sym::C]) {
         Sym::template step<K>(tr, sr, acc, racc);
         SymSteps<Sym, T, K + 1>::run(tr, sr, acc, racc);
@@ -1165,9 +1235,20 @@ struct SymSteps {
 };
 template <class Sym, typename T>
 struct SymSteps<Sym, T, 16> {
-    __device__ __forceinline__ static void run(const T (&)[Sym::R], const T (&)[Sym::R], T (&)[Sym::C],
-                                               T (&)[Sym::C]) {}
+    template <class Src>
+    __device__ __forceinline__ static void run(const T (&)[Sym::R], const Src&, T (&)[Sym::C], T (&)[Sym::C]) {}
 };
+
+// Source fields a symmetric step takes by DPP rotation (bit f: field f; the
+// rest by indexed LDS reads).  A DPP operand costs the VALU half an issue slot
+// more per use; an LDS read costs LDS bandwidth (64 lanes x 4 bytes per field
+// and step).  Float passes rotate the coordinates, which every pair needs
+// first, and read the other fields from LDS: rotating every field left the
+// Stokes step at the VALU's half-rate DPP issue, reading every field needs
+// about as much LDS bandwidth as the CU has; double passes read every field
+// from LDS (a double rotation is two DPP moves).
+template <typename T>
+constexpr unsigned sym_dpp_fields() { return sizeof(T) == 4 ? 0x7u : 0x0u; }
 
 struct SymArgs {
     int nblocks;
@@ -1181,7 +1262,7 @@ template <class Sym, typename T>
 __device__ __forceinline__ void sym_far_body(const KArgs& a, const SymArgs& sa, int blk) {
     constexpr int R = Sym::R, C = Sym::C;
     static_assert(kTile == kTPB && kTile == 256, "one target and one staged source per thread, four waves");
-    __shared__ T srec[kTile * R];
+    __shared__ T srec[R * kTile];  // the source tile, field-major: field f of source j at srec[f * kTile + j]
     __shared__ T sracc[C * kTile];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int first = sa.blocks[2 * blk], cnt = sa.blocks[2 * blk + 1];
@@ -1194,11 +1275,15 @@ __device__ __forceinline__ void sym_far_body(const KArgs& a, const SymArgs& sa, 
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0;
     T* rev = static_cast<T*>(sa.rev);
+    constexpr unsigned DPP = sym_dpp_fields<T>();
+    SymSrc<T, R, DPP> src;
+    src.lds = srec;
+    src.l16 = lane & 15;
     for (int it = first; it < first + cnt; ++it) {
         const int tb = sa.items[3 * it + 1], p = sa.items[3 * it + 2];
         __syncthreads();  // the previous tile pair is done with the LDS
 #pragma unroll
-        for (int f = 0; f < R; ++f) srec[tid * R + f] = rec[((int64_t)tb * kTile + tid) * R + f];
+        for (int f = 0; f < R; ++f) srec[f * kTile + tid] = rec[((int64_t)tb * kTile + tid) * R + f];
 #pragma unroll
         for (int c = 0; c < C; ++c) sracc[c * kTile + tid] = T(0);
         __syncthreads();
@@ -1211,13 +1296,15 @@ __device__ __forceinline__ void sym_far_body(const KArgs& a, const SymArgs& sa, 
 #pragma unroll 1
             for (int rr = 0; rr < 4; ++rr) {
                 // row r of the wave holds row (r + rr) mod 4 of the quarter
-                const int j = 64 * q + ((((lane >> 4) + rr) & 3) << 4) + (lane & 15);
-                T sr[R], racc[C];
+                src.jb = 64 * q + ((((lane >> 4) + rr) & 3) << 4);
+                const int j = src.jb + src.l16;
 #pragma unroll
-                for (int f = 0; f < R; ++f) sr[f] = srec[j * R + f];
+                for (int f = 0; f < R; ++f)
+                    if ((DPP >> f) & 1u) src.own[f] = srec[f * kTile + j];
+                T racc[C];
 #pragma unroll
                 for (int c = 0; c < C; ++c) racc[c] = sracc[c * kTile + j];
-                SymSteps<Sym, T, 0>::run(tr, sr, facc, racc);
+                SymSteps<Sym, T, 0>::run(tr, src, facc, racc);
 #pragma unroll
                 for (int c = 0; c < C; ++c) sracc[c * kTile + j] = racc[c];
             }
@@ -1233,41 +1320,50 @@ __device__ __forceinline__ void sym_far_body(const KArgs& a, const SymArgs& sa, 
     for (int c = 0; c < C; ++c) sa.fwd[((int64_t)blk * C + c) * kTile + tid] = acc[c];
 }
 
-// symmetric far blocks first, then the near-field blocks of the pass
+// symmetric far blocks first, then the near-field blocks of the pass.  Left
+// alone, the compiler hoists the LDS reads of a whole row rotation ahead of
+// its 16 steps (up to 134 VGPRs, 3 waves per SIMD for the float Laplace double
+// layer); the float passes are held to 8 waves per SIMD.
 template <class Op, class Sym, typename T>
-__global__ __launch_bounds__(kTPB) void sym_pass_pairs(KArgs a, SymArgs sa) {
+__global__ __launch_bounds__(kTPB) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 8 : 1)))
+void sym_pass_pairs(KArgs a, SymArgs sa) {
     if ((int)blockIdx.x < sa.nblocks) sym_far_body<Sym, T>(a, sa, blockIdx.x);
     else near_body<Op, T>(a, (int)blockIdx.x - sa.nblocks);
 }
 
-// Sum of the symmetric pass per target, in a fixed order: the forward slots
-// of its tile's blocks, the reverse slots of its tile's pairs, the near-field
-// split slots; then the terms of epilogue().
+// Sum of the symmetric pass per target, in a fixed order, then the terms of
+// epilogue(): the forward slots of its tile's blocks, the reverse slots of the
+// far tile pairs with its tile as the source tile (about T/2 of them), the
+// near-field split slots; each kind split over the 8 thread groups of the
+// target as in epilogue().
 template <int C, typename RT>
-__global__ void sym_epilogue(int64_t n, const int32_t* __restrict__ fwd_start, const double* __restrict__ fwd,
-                             const int32_t* __restrict__ rev_start, const RT* __restrict__ rev, int nsplit,
-                             const double* __restrict__ partial, const double* __restrict__ tw, const double* base,
-                             double base_scale, const double* __restrict__ comp, double comp_scale,
-                             const double* __restrict__ nrm, double add0, double add1, double add2, double* out,
-                             const int32_t* __restrict__ perm) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t t = i / kTile, j = i % kTile;
-    const double cs = comp ? comp_scale * comp[0] : 0.0;
-    const int64_t o = perm ? (int64_t)perm[i] : i;
-    const int b0 = fwd_start[t], b1 = fwd_start[t + 1], p0 = rev_start[t], p1 = rev_start[t + 1];
+__global__ __launch_bounds__(kEpiThreads) void sym_epilogue(
+    int64_t n, const int32_t* __restrict__ fwd_start, const double* __restrict__ fwd,
+    const int32_t* __restrict__ rev_start, const RT* __restrict__ rev, int nsplit,
+    const double* __restrict__ partial, const double* __restrict__ tw, const double* base, double base_scale,
+    const double* __restrict__ comp, double comp_scale, const double* __restrict__ nrm, double add0, double add1,
+    double add2, double* out, const int32_t* __restrict__ perm) {
+    static_assert(kTile % kEpiTargets == 0, "a block's targets lie in one tile");
+    const int g = threadIdx.x / kEpiTargets, jj = threadIdx.x % kEpiTargets;
+    const int64_t i = (int64_t)blockIdx.x * kEpiTargets + jj;
+    double v[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) {
-        double v = 0.0;
-        for (int b = b0; b < b1; ++b) v += fwd[((int64_t)b * C + c) * kTile + j];
-        for (int p = p0; p < p1; ++p) v += (double)rev[((int64_t)p * C + c) * kTile + j];
-        for (int s = 0; s < nsplit; ++s) v += partial[((int64_t)(nsplit + s) * C + c) * n + i];
-        if (tw) v *= tw[i];
-        if (base) v += base_scale * base[c * n + i];
-        if (comp) v += cs * (C == 3 ? nrm[c * n + i] : 1.0);
-        v += (c == 0 ? add0 : (c == 1 ? add1 : add2));
-        out[c * n + o] = v;
+    for (int c = 0; c < C; ++c) v[c] = 0.0;
+    if (i < n) {
+        const int64_t t = i / kTile, j = i % kTile;
+        const int b1 = fwd_start[t + 1], p1 = rev_start[t + 1];
+        for (int b = fwd_start[t] + g; b < b1; b += kEpiGroups)
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] += fwd[((int64_t)b * C + c) * kTile + j];
+        for (int p = rev_start[t] + g; p < p1; p += kEpiGroups)
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] += (double)rev[((int64_t)p * C + c) * kTile + j];
+        for (int sl = g; sl < nsplit; sl += kEpiGroups)
+#pragma unroll
+            for (int c = 0; c < C; ++c) v[c] += partial[((int64_t)(nsplit + sl) * C + c) * n + i];
     }
+    epi_combine<C>(v, g, jj);
+    if (g == 0 && i < n) epi_finish<C>(n, i, v, tw, base, base_scale, comp, comp_scale, nrm, add0, add1, add2, out, perm);
 }
 
 KArgs make_args(const Plan& P, const PassDesc& d, int nsplit, double cut) {
@@ -1324,7 +1420,8 @@ bool launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int fami
     using Sym = typename SymOf<Op>::type;
     if constexpr (!std::is_same<Sym, void>::value) {
         const int k = mixed ? 1 : 0;
-        if ((P.symmetric & Sym::kFamilyBit) && P.sym_items[k] && P.sym_nblocks[k] > 0 && !a.dl_tgt) {
+        const int kind = mixed ? Sym::kFamilyBit : Sym::kFamilyBit << 2;  // SDBIE_SYM_* of this pass
+        if ((P.symmetric & kind) && P.sym_items[k] && P.sym_nblocks[k] > 0 && !a.dl_tgt) {
             SymArgs sa;
             sa.nblocks = P.sym_nblocks[k];
             sa.items = P.sym_items[k];
@@ -1371,7 +1468,8 @@ bool launch_pair_kernels(const Plan& P, const KArgs& a, hipStream_t st, int fami
 // tile-pair) partials summed per target, then the pass's extra terms.
 template <int C>
 void launch_epilogue(const Plan& P, const PassDesc& d, int S, bool sym, hipStream_t st) {
-    const unsigned eb = (unsigned)((P.n + 255) / 256);
+    const unsigned eb = (unsigned)((P.n + kEpiTargets - 1) / kEpiTargets);
+    const dim3 et(kEpiThreads);
     const double* add = d.add_const;
     const double a0 = add ? add[0] : 0.0, a1 = add && C > 1 ? add[1] : 0.0, a2 = add && C > 2 ? add[2] : 0.0;
     const double* tw = d.target_weight ? (const double*)P.w : nullptr;
@@ -1379,19 +1477,19 @@ void launch_epilogue(const Plan& P, const PassDesc& d, int S, bool sym, hipStrea
     if (sym) {
         const int k = d.mixed ? 1 : 0;
         if (d.mixed)
-            hipLaunchKernelGGL((sym_epilogue<C, float>), dim3(eb), dim3(256), 0, st, P.n,
+            hipLaunchKernelGGL((sym_epilogue<C, float>), dim3(eb), et, 0, st, P.n,
                                (const int32_t*)P.sym_fwd_start[k], (const double*)P.sym_fwd,
                                (const int32_t*)P.sym_rev_start[k], (const float*)P.sym_rev, S,
                                (const double*)P.partial, tw, d.base, d.base_scale, d.comp, d.comp_scale,
                                (const double*)P.nrm, a0, a1, a2, d.out, perm);
         else
-            hipLaunchKernelGGL((sym_epilogue<C, double>), dim3(eb), dim3(256), 0, st, P.n,
+            hipLaunchKernelGGL((sym_epilogue<C, double>), dim3(eb), et, 0, st, P.n,
                                (const int32_t*)P.sym_fwd_start[k], (const double*)P.sym_fwd,
                                (const int32_t*)P.sym_rev_start[k], (const double*)P.sym_rev, S,
                                (const double*)P.partial, tw, d.base, d.base_scale, d.comp, d.comp_scale,
                                (const double*)P.nrm, a0, a1, a2, d.out, perm);
     } else {
-        hipLaunchKernelGGL((epilogue<C>), dim3(eb), dim3(256), 0, st, P.n, 2 * S, (const double*)P.partial, tw,
+        hipLaunchKernelGGL((epilogue<C>), dim3(eb), et, 0, st, P.n, 2 * S, (const double*)P.partial, tw,
                            d.base, d.base_scale, d.comp, d.comp_scale, (const double*)P.nrm, a0, a1, a2, d.out,
                            perm);
     }
@@ -1482,7 +1580,8 @@ void launch_stokes_pass(const Plan& P, const PassDesc& d, hipStream_t st) {
             throw Error(SDBIE_ERR_ARG, "transposed Stokes pass: double and single layer of one density");
         if (d.mixed) launch_pair_kernels<StokesTNSLOp<float>, float>(P, a, st, 1, 16 | 2 | 1, true);
         else launch_pair_kernels<StokesTNSLOp<double>, double>(P, a, st, 1, 16 | 2 | 1, false);
-        hipLaunchKernelGGL((epilogue<6>), dim3((unsigned)((P.n + 255) / 256)), dim3(256), 0, st, P.n, 2 * S,
+        hipLaunchKernelGGL((epilogue<6>), dim3((unsigned)((P.n + kEpiTargets - 1) / kEpiTargets)), dim3(kEpiThreads),
+                           0, st, P.n, 2 * S,
                            (const double*)P.partial, d.target_weight ? (const double*)P.w : nullptr, nullptr, 0.0,
                            nullptr, 0.0, (const double*)P.nrm, 0.0, 0.0, 0.0, d.out,
                            d.scatter ? (const int32_t*)P.perm : nullptr);
@@ -1539,18 +1638,19 @@ void launch_grad_pass(const Plan& P, const GradDesc& g, hipStream_t st) {
     a.g_l2 = g.lam2;
     a.g_mu = g.mu;
     a.g_K = g.K;
-    const unsigned eb = (unsigned)((P.n + 255) / 256);
+    const unsigned eb = (unsigned)((P.n + kEpiTargets - 1) / kEpiTargets);
+    const dim3 et(kEpiThreads);
     {
         // node as target: A_m = sum_j g_mj
         launch_pair_kernels<GradOp<false>, double>(P, a, st, 2, 0, false);
-        hipLaunchKernelGGL((epilogue<3>), dim3(eb), dim3(256), 0, st, P.n, 2 * S, (const double*)P.partial,
+        hipLaunchKernelGGL((epilogue<3>), dim3(eb), et, 0, st, P.n, 2 * S, (const double*)P.partial,
                            (const double*)nullptr, (const double*)nullptr, 0.0, (const double*)nullptr, 0.0,
                            (const double*)P.nrm, 0.0, 0.0, 0.0, g.out, (const int32_t*)nullptr);
         SDBIE_LAUNCHED();
         // node as source: out = sum_i g_im - A_m
         launch_pair_kernels<GradOp<true>, double>(P, a, st, 2, 16, false);
     }
-    hipLaunchKernelGGL((epilogue<3>), dim3(eb), dim3(256), 0, st, P.n, 2 * S, (const double*)P.partial,
+    hipLaunchKernelGGL((epilogue<3>), dim3(eb), et, 0, st, P.n, 2 * S, (const double*)P.partial,
                        (const double*)nullptr, (const double*)g.out, -1.0, (const double*)nullptr, 0.0,
                        (const double*)P.nrm, 0.0, 0.0, 0.0, g.out, (const int32_t*)nullptr);
     SDBIE_LAUNCHED();

@@ -39,7 +39,14 @@ def test_header_constants_match_the_binding():
     src = open(HEADER).read()
     defs = dict(re.findall(r"^#define\s+(SDBIE_[A-Z0-9_]+)\s+(\S+)", src, flags=re.M))
     assert int(defs["SDBIE_SYM_LAPLACE"]) == B.SYM_LAPLACE and int(defs["SDBIE_SYM_STOKES"]) == B.SYM_STOKES
-    assert defs["SDBIE_SYM_DEFAULT"] == "SDBIE_SYM_LAPLACE" and B.SYM_DEFAULT == B.SYM_LAPLACE
+    assert int(defs["SDBIE_SYM_LAPLACE_F64"]) == B.SYM_LAPLACE_F64
+    assert int(defs["SDBIE_SYM_STOKES_F64"]) == B.SYM_STOKES_F64 and int(defs["SDBIE_SYM_ALL"]) == B.SYM_ALL
+    assert B.SYM_ALL == B.SYM_LAPLACE | B.SYM_STOKES | B.SYM_LAPLACE_F64 | B.SYM_STOKES_F64
+    m = re.search(r"^#define\s+SDBIE_SYM_DEFAULT\s+\((.*)\)\s*$", open(HEADER).read(), flags=re.M)
+    default = 0
+    for name in m.group(1).split("|"):
+        default |= int(defs[name.strip()])
+    assert default == B.SYM_DEFAULT
     assert int(defs["SDBIE_NOALLOC_MAX_NODES"]) == B.NOALLOC_MAX_NODES
 
 

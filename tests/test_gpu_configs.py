@@ -311,5 +311,5 @@ def test_layers_beyond_the_symmetric_limit(sd):
     w = np.full(N, 4.0 * math.pi / N)
     delta = 3.0 * math.sqrt(4.0 * math.pi / N)
     t = np.sort(rng.choice(N, size=24, replace=False))
-    check_all_layers(sd, x, x.copy(), w, delta, seed=72, targets=t, symmetric=sd.SYM_LAPLACE | sd.SYM_STOKES,
+    check_all_layers(sd, x, x.copy(), w, delta, seed=72, targets=t, symmetric=sd.SYM_ALL,
                      tol32=max(TOL32, 4 * EPS32 / delta))

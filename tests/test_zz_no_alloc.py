@@ -43,6 +43,7 @@ def test_noalloc_matches_plan_on_two_calls(sd):
         x, n, w = dev(S.x), dev(S.n), dev(S.w)
         q = fields.random_vector(S.N, seed)
         plan = sd.Plan(x, n, w, delta)
+        plan.set_symmetric(0)  # the allocation-free sums run the one-direction kernels
         geo = O.Geometry(S.x, S.n, S.w, delta)
         rows = np.arange(0, S.N, max(1, S.N // 97))
         for layer, kind in (("sl", O.SSL), ("dl_raw", O.SDL), ("dl_sub", O.SDLS)):
