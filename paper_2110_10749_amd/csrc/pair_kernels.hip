@@ -1055,9 +1055,9 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue(int64_t n, int nslots, c
 // tile pair {a, b} (a < b, every pair beyond the cutoff) is evaluated once:
 // every lane of a block holds one target of tile a and, in turn, one source
 // of tile b.  Within a wave the sources rotate across the 16 lanes of each
-// row: at step K lane l meets the source of lane (l - K) mod 16, its
-// coordinates taken by a DPP row rotation and its other fields read from the
-// tile staged in LDS at that index (SymSrc), so at every step each lane
+// row: at step K lane l meets the source of lane (l - K) mod 16, its fields
+// read from the tile staged in LDS at that index (SymSrc; fields can also be
+// taken by DPP row rotations of the lane's own record), so at every step each lane
 // evaluates one pair, adds the forward contribution to its own target and
 // hands the reverse one back to the source's lane through the inverse
 // rotation.  A wave meets its 64
@@ -1242,13 +1242,20 @@ struct SymSteps<Sym, T, 16> {
 // Source fields a symmetric step takes by DPP rotation (bit f: field f; the
 // rest by indexed LDS reads).  A DPP operand costs the VALU half an issue slot
 // more per use; an LDS read costs LDS bandwidth (64 lanes x 4 bytes per field
-// and step).  Float passes rotate the coordinates, which every pair needs
-// first, and read the other fields from LDS: rotating every field left the
-// Stokes step at the VALU's half-rate DPP issue, reading every field needs
-// about as much LDS bandwidth as the CU has; double passes read every field
-// from LDS (a double rotation is two DPP moves).
+// and step) and no VALU slot.  Measured at h = 1/64 (ms per launch, float
+// Stokes single layer / double layer / Laplace double layer): every field by
+// DPP 2.24 / 2.48 / 1.59, the coordinates by DPP 1.92 / 1.96 / 1.45, every
+// field from LDS 1.80 / 1.92 / 1.39 (the mixed solve 116.5 ms against 119.4 ms
+// with the coordinates by DPP); a double rotation is two DPP moves.  Every
+// field comes from LDS by default; the reverse sums still rotate by DPP.
+#ifndef SDBIE_SYM_DPP_F32
+#define SDBIE_SYM_DPP_F32 0x0u
+#endif
+#ifndef SDBIE_SYM_DPP_F64
+#define SDBIE_SYM_DPP_F64 0x0u
+#endif
 template <typename T>
-constexpr unsigned sym_dpp_fields() { return sizeof(T) == 4 ? 0x7u : 0x0u; }
+constexpr unsigned sym_dpp_fields() { return sizeof(T) == 4 ? SDBIE_SYM_DPP_F32 : SDBIE_SYM_DPP_F64; }
 
 struct SymArgs {
     int nblocks;
