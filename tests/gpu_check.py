@@ -49,7 +49,11 @@ def check_all_layers(sd, x, n, w, delta, seed, mu=1.3, targets=None, precs=("fp6
             if targets is not None:
                 gl, gs = gl[targets], gs[:, targets]
             el, es = relerr(gl, ref_l), relerr(gs, ref_s)
-            tol = TOL64 if prec == "fp64" else tol32
+            # float pairs: the rounding of the coordinates, EPS32 |x|, against the
+            # smallest smoothed distances (~delta) bounds a pair's relative error at
+            # about 4 EPS32 max|x| / delta (the raw double layer: / delta^2, its
+            # D.n_j = O(r^2) cancels)
+            tol = TOL64 if prec == "fp64" else max(tol32, 4 * EPS32 * np.max(np.abs(x)) / delta)
             if prec == "mixed" and name == "dl_raw":
                 tol = max(tol32, 4 * EPS32 * np.max(np.abs(x)) / delta**2)
             print(f"N={N} {name:7s} {prec:5s} laplace {el:.2e} stokes {es:.2e}", flush=True)

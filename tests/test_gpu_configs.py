@@ -29,7 +29,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_check import EPS32, TOL32, check_all_layers, dev
+from gpu_check import check_all_layers, dev
 from oracle import oracle as O
 from workloads import exact, fields, surfaces
 
@@ -302,8 +302,8 @@ def test_layers_beyond_the_symmetric_limit(sd):
     # at a time whatever the mask: 600000 seeded points on the unit sphere,
     # every layer against the oracle on 24 sampled rows.  delta = 0.0137 here
     # (a grid of h ~ 1/220): the float rounding of the coordinates, EPS32 |x|,
-    # is 4e-6 of the smallest smoothed distances, so the float-pair bar is
-    # 4 EPS32 max|x| / delta (1.7e-5) instead of the 3e-6 of the paper's grids
+    # is 4e-6 of the smallest smoothed distances, and the float-pair bar of
+    # check_all_layers, 4 EPS32 max|x| / delta, is 1.7e-5
     N = 600000
     rng = np.random.default_rng(71)
     x = rng.normal(size=(3, N))
@@ -311,5 +311,4 @@ def test_layers_beyond_the_symmetric_limit(sd):
     w = np.full(N, 4.0 * math.pi / N)
     delta = 3.0 * math.sqrt(4.0 * math.pi / N)
     t = np.sort(rng.choice(N, size=24, replace=False))
-    check_all_layers(sd, x, x.copy(), w, delta, seed=72, targets=t, symmetric=sd.SYM_ALL,
-                     tol32=max(TOL32, 4 * EPS32 / delta))
+    check_all_layers(sd, x, x.copy(), w, delta, seed=72, targets=t, symmetric=sd.SYM_ALL)
