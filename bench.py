@@ -24,10 +24,12 @@ solve's (p, u) in both coupled equations that its pair sums give (the error
 of the GPU solution against the FP64 oracle).
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload sphere-h64|perturbed-h128]
+    python bench.py --passes          (per-pass kernel times only)
 
 The second workload is the large surface (N = 351866); one solve takes minutes,
 so run it with --steps 1 --warmup 0 --no-fp64 (SDBIE_DEBUG=1 prints the
-interface steps as they complete).
+interface steps as they complete).  --passes times every single layer pass of
+the workload's surface, float and double pairs, one-direction and symmetric.
 """
 from __future__ import annotations
 

@@ -242,7 +242,11 @@ int stokes_solve(sdbie_plan plan, const sdbie_params* prm, const double U[3], co
  * interface map (outer = 1).  Outputs p (device [n]), u (device [3][n])
  * and the drag (host double[3]) by eq. (drag_int), D = sum_j w_j f_j.
  * f_extra (device [3][n] or NULL) is a prescribed extra traction (the
- * paper's benchmark adds the exact viscous traction of its test problem). */
+ * paper's benchmark adds the exact viscous traction of its test problem).
+ * NOT_CONVERGED when the interface residual or a final local solve misses
+ * its tolerance (with inexact interface products, relax_outer = 1, the
+ * local solves inside the products only make the products inexact: the
+ * final solves and the true interface residual decide). */
 int ddm_solve(sdbie_plan plan, const sdbie_params* prm, const double U[3], const double* f_extra,
               double* p, double* u, double drag[3], const sdbie_opts* opts, sdbie_info* info,
               void* stream);

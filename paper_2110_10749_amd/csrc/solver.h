@@ -109,6 +109,11 @@ struct Ctx {
     // solves whose results only enter an interface product, when the final
     // solves and the true interface residual certify the answer)
     bool estimate_only = false;
+    // in_product: the local solves of T(0) and of the interface products under
+    // inexact products; the final solves and the true interface residual
+    // decide convergence, so a product's local solve that misses its own
+    // tolerance only makes the product inexact (and costs correction cycles)
+    bool in_product = false;
     // index of the Krylov basis vector the operator is being applied to (-1: a residual)
     int krylov_index = -1;
     // deflation of the Stokes local solves (opts.recycle): rc_cur is set around

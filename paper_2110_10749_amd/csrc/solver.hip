@@ -346,7 +346,7 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op3, co
         }
         info.gmres_iters += m;
         info.relres = ch;
-        if (ch > tol) converged = false;
+        if (ch > tol && !in_product) converged = false;
         return;
     }
     if (loose32) {
@@ -367,7 +367,7 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op3, co
         if (mixed) info.refine_steps += g.checks;
         info.gmres_iters += g.iters;
         info.relres = g.relres;
-        if (!g.conv) converged = false;
+        if (!g.conv && !in_product) converged = false;
         return;
     }
     const double b_norm = norm(b, L);
@@ -401,7 +401,7 @@ void Ctx::solve(const std::function<void(const double*, double*, bool)>& op3, co
     }
     info.refine_steps += step;
     info.relres = rel;
-    if (rel > tol) converged = false;
+    if (rel > tol && !in_product) converged = false;
 }
 
 // ------------------------------------------------------------------------------
@@ -604,10 +604,12 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
     // the switch (tol_mixed), well below what an interface product needs.
     // The final solves still end on double-pair residuals and the true
     // interface residual decides convergence, correction cycles included.
-    const bool est_save = estimate_only;
+    const bool est_save = estimate_only, prod_save = in_product;
     estimate_only = relax && image && o.prec == SDBIE_MIXED && o.mixed_mode == 2;
+    in_product = relax;
     stokes(prm, U, pstk, fx, ul, false, r2, r1 == nullptr);  // T(0): p = 0 without a Darcy source
     estimate_only = est_save;
+    in_product = prod_save;
     dev_normal_component(P, ul, t0, s);
     const double t0n = relax ? norm(t0, n) : 0.0;
     if (image) {
@@ -637,6 +639,7 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
                          ++outer_steps, rr, tol_local > 0.0 ? tol_local : o.tol_gmres,
                          loose32 ? " (float pairs)" : "");
         estimate_only = relax && image && o.prec == SDBIE_MIXED && o.mixed_mode == 2;
+        in_product = relax;
         darcy(prm, y, pl, false, nullptr, remove_mean);
         double* slot = image && kslot >= 0 ? P.image_out + (int64_t)kslot * ld_img : nullptr;
         if (slot) {
@@ -661,6 +664,7 @@ void Ctx::ddm_outer(const sdbie_params& prm, const double U[3], const double* fx
         tol_local = tl_save;
         loose32 = l_save;
         estimate_only = est_save;
+        in_product = prod_save;
     };
     auto finish = [&]() {
         double bD = 0.0, bS = 0.0;  // norms of the final right-hand sides, from the image basis
