@@ -198,6 +198,7 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
     double beta = norm(r, L);
     res.relres = beta / bnorm;
     const double rel0 = res.relres;
+    int n64 = 0;  // products with double pairs (diagnostics)
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), e(m + 1), col(2 * (m + 1) + 1), y(m);
     auto Hat = [&](int i, int j) -> double& { return H[(size_t)i * m + j]; };
     int last_k = 0;
@@ -213,6 +214,7 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
             double* vk = ws.V + (int64_t)k * L;
             const bool m32 = all32 || res.relres <= relax;
             cycle32 = cycle32 || m32;
+            n64 += !m32;
             krylov_index = k;
             op(vk, w, m32, res.relres);
             krylov_index = -1;
@@ -306,8 +308,8 @@ GmresOut Ctx::gmres(const GmresWS& ws, const GmresOp& op, const double* b, doubl
     res.conv = res.relres <= tol;
     SDBIE_HIP(hipStreamSynchronize(s));
     if (debug_level() > 1)
-        std::fprintf(stderr, "[sdbie] gmres L=%lld start %.1e iters=%d relres=%.3e tol=%.1e\n", (long long)L, rel0,
-                     res.iters, res.relres, tol);
+        std::fprintf(stderr, "[sdbie] gmres L=%lld start %.1e iters=%d (double pairs %d) relres=%.3e tol=%.1e\n",
+                     (long long)L, rel0, res.iters, n64, res.relres, tol);
     return res;
 }
 
