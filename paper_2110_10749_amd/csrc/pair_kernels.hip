@@ -239,6 +239,13 @@ __host__ __device__ constexpr int unroll_of() {
     return u;
 }
 
+// Pair terms a lane sums in T before it adds the sum into its double
+// accumulator (flush()): 16 in float, so the float rounding of the running
+// sums stays at the level of the rounding of the terms themselves; a whole
+// tile or unit in double, where the running sums are double already.
+template <typename T>
+__host__ __device__ constexpr int block_terms() { return sizeof(T) == 4 ? 16 : kTile; }
+
 // --------------------------------------------------------------------------
 // Laplace: DL term c_dl * w_j (q_j - SUB q_i) (D.n_j) s2/r^3, SL term c_sl * w_j g_j s1/r
 // record: x y z q | nx ny nz g   (SL only: x y z g); n and g carry c w_j
@@ -778,13 +785,18 @@ __device__ __forceinline__ void far_body(const KArgs& a, int blk) {
     const int t1 = t0 + a.tiles_per_split < a.ntiles ? t0 + a.tiles_per_split : a.ntiles;
     const uint8_t* row = a.mask + (int64_t)b * a.ntiles;
     const src_ptr<T> rec = (src_ptr<T>)a.rec;
+    constexpr int B = block_terms<T>();
+    static_assert(kTile % B == 0 && B % Op::U == 0, "blocks of whole unrolled steps");
     for (int t = t0; t < t1; ++t) {
         if (row[t]) continue;  // uniform
         const src_ptr<T> rt = rec + (int64_t)t * kTile * Op::R;
 #pragma unroll 1
-        for (int jj = 0; jj < kTile; jj += Op::U)
-            pair_group<Op, T, false, Op::U>(op, rt + jj * Op::R, id, id2, rc2);
-        op.flush();
+        for (int jb = 0; jb < kTile; jb += B) {
+#pragma unroll 1
+            for (int jj = jb; jj < jb + B; jj += Op::U)
+                pair_group<Op, T, false, Op::U>(op, rt + jj * Op::R, id, id2, rc2);
+            op.flush();
+        }
     }
     if (i < a.n) op.store(a, split, i);
 }
@@ -837,23 +849,28 @@ __device__ __forceinline__ void far_lds_body(const KArgs& a, int blk) {
         g = rec + (int64_t)(tn < t1 ? tn : t) * kTile * Q + threadIdx.x;
 #pragma unroll
         for (int c = 0; c < Q; ++c) pf[c] = g[c * kTPB];
+        constexpr int B = block_terms<T>();
+        static_assert(kTile % B == 0 && B % Op::U == 0, "blocks of whole unrolled steps");
 #pragma unroll 1
-        for (int jj = 0; jj < kTile; jj += Op::U) {
+        for (int jb = 0; jb < kTile; jb += B) {
+#pragma unroll 1
+            for (int jj = jb; jj < jb + B; jj += Op::U) {
 #pragma unroll
-            for (int u = 0; u < Op::U; ++u) {
-                T r[R];
+                for (int u = 0; u < Op::U; ++u) {
+                    T r[R];
 #pragma unroll
-                for (int c = 0; c < Q; ++c) {
-                    const f4 v = tile[(jj + u) * Q + c];
-                    r[4 * c] = v[0];
-                    r[4 * c + 1] = v[1];
-                    r[4 * c + 2] = v[2];
-                    r[4 * c + 3] = v[3];
+                    for (int c = 0; c < Q; ++c) {
+                        const f4 v = tile[(jj + u) * Q + c];
+                        r[4 * c] = v[0];
+                        r[4 * c + 1] = v[1];
+                        r[4 * c + 2] = v[2];
+                        r[4 * c + 3] = v[3];
+                    }
+                    op.template pair<false>(static_cast<const T*>(r), id, id2, rc2);
                 }
-                op.template pair<false>(static_cast<const T*>(r), id, id2, rc2);
             }
+            op.flush();
         }
-        op.flush();
         t = tn;
     }
     if (i < a.n) op.store(a, split, i);
@@ -877,6 +894,8 @@ __device__ __forceinline__ void near_body(const KArgs& a, int blk) {
     constexpr int FU = Op::U > 1 ? Op::U / 2 : 1;
     static_assert(kNearUnit % NU == 0 && kNearUnit % FU == 0, "unroll must divide the near unit");
     static_assert(kNearUnit == 64, "one wave of targets per unit test");
+    constexpr int B = block_terms<T>() < kNearUnit ? block_terms<T>() : kNearUnit;
+    static_assert(kNearUnit % B == 0 && B % NU == 0 && B % FU == 0, "blocks of whole unrolled steps");
     const int split = blk % a.nsplit;
     const int b = blk / a.nsplit;
     const int64_t i = (int64_t)b * kTPB + threadIdx.x;
@@ -921,16 +940,19 @@ __device__ __forceinline__ void near_body(const KArgs& a, int blk) {
                     }
                     far_unit = d2 >= a.rcu2;
                 }
-                if (far_unit) {
 #pragma unroll 1
-                    for (int jj = 0; jj < kNearUnit; jj += FU)
-                        pair_group<Op, T, false, FU>(op, ru + jj * Op::R, id, id2, rc2);
-                } else {
+                for (int jb = 0; jb < kNearUnit; jb += B) {
+                    if (far_unit) {
 #pragma unroll 1
-                    for (int jj = 0; jj < kNearUnit; jj += NU)
-                        pair_group<Op, T, true, NU>(op, ru + jj * Op::R, id, id2, rc2);
+                        for (int jj = jb; jj < jb + B; jj += FU)
+                            pair_group<Op, T, false, FU>(op, ru + jj * Op::R, id, id2, rc2);
+                    } else {
+#pragma unroll 1
+                        for (int jj = jb; jj < jb + B; jj += NU)
+                            pair_group<Op, T, true, NU>(op, ru + jj * Op::R, id, id2, rc2);
+                    }
+                    op.flush();
                 }
-                op.flush();
             }
             ++rank;
         }
@@ -1189,18 +1211,19 @@ struct SymStokes {
         }
         T rc[3];
         if constexpr (SL) {
-            const T q = ir2 * ir;
+            // (1/r) [f + D (1/r^2) ((u.D)(D.n)/r^2 + D.f)] in each direction: 1/r
+            // multiplies the sum, not each of its terms
             const T fsx = sr.template get<K, FX>(), fsy = sr.template get<K, FY>(), fsz = sr.template get<K, FZ>();
             const T dfs = fma(dx, fsx, fma(dy, fsy, dz * fsz));
             const T dft = fma(dx, tr[FX], fma(dy, tr[FY], dz * tr[FZ]));
-            const T ef = (DL ? fma(ud * dns, ir2, dfs) : dfs) * q;
-            const T er = (DL ? fma(udr * dnt, ir2, dft) : dft) * q;
-            acc[0] = fma(fsx, ir, fma(ef, dx, acc[0]));
-            acc[1] = fma(fsy, ir, fma(ef, dy, acc[1]));
-            acc[2] = fma(fsz, ir, fma(ef, dz, acc[2]));
-            rc[0] = fma(er, dx, tr[FX] * ir);
-            rc[1] = fma(er, dy, tr[FY] * ir);
-            rc[2] = fma(er, dz, tr[FZ] * ir);
+            const T ef = (DL ? fma(ud * dns, ir2, dfs) : dfs) * ir2;
+            const T er = (DL ? fma(udr * dnt, ir2, dft) : dft) * ir2;
+            acc[0] = fma(fma(ef, dx, fsx), ir, acc[0]);
+            acc[1] = fma(fma(ef, dy, fsy), ir, acc[1]);
+            acc[2] = fma(fma(ef, dz, fsz), ir, acc[2]);
+            rc[0] = fma(er, dx, tr[FX]) * ir;
+            rc[1] = fma(er, dy, tr[FY]) * ir;
+            rc[2] = fma(er, dz, tr[FZ]) * ir;
         } else {
             const T k4 = ir * ir2 * ir2;
             const T cf = ud * dns * k4, cr = udr * dnt * k4;
@@ -1269,8 +1292,9 @@ template <class Sym, typename T>
 __device__ __forceinline__ void sym_far_body(const KArgs& a, const SymArgs& sa, int blk) {
     constexpr int R = Sym::R, C = Sym::C;
     static_assert(kTile == kTPB && kTile == 256, "one target and one staged source per thread, four waves");
+    static_assert(block_terms<T>() >= 16, "a row rotation of 16 steps sums in T");
     __shared__ T srec[R * kTile];  // the source tile, field-major: field f of source j at srec[f * kTile + j]
-    __shared__ T sracc[C * kTile];
+    __shared__ double sracc[C * kTile];  // reverse sums of the tile pair, one 16-step rotation at a time
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int first = sa.blocks[2 * blk], cnt = sa.blocks[2 * blk + 1];
     const int ta = sa.items[3 * first];
@@ -1292,11 +1316,8 @@ __device__ __forceinline__ void sym_far_body(const KArgs& a, const SymArgs& sa, 
 #pragma unroll
         for (int f = 0; f < R; ++f) srec[f * kTile + tid] = rec[((int64_t)tb * kTile + tid) * R + f];
 #pragma unroll
-        for (int c = 0; c < C; ++c) sracc[c * kTile + tid] = T(0);
+        for (int c = 0; c < C; ++c) sracc[c * kTile + tid] = 0.0;
         __syncthreads();
-        T facc[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) facc[c] = T(0);
 #pragma unroll 1
         for (int ph = 0; ph < 4; ++ph) {
             const int q = (wave + ph) & 3;  // the four waves take the four quarters of the sources
@@ -1308,20 +1329,21 @@ __device__ __forceinline__ void sym_far_body(const KArgs& a, const SymArgs& sa, 
 #pragma unroll
                 for (int f = 0; f < R; ++f)
                     if ((DPP >> f) & 1u) src.own[f] = srec[f * kTile + j];
-                T racc[C];
+                T facc[C], racc[C];
 #pragma unroll
-                for (int c = 0; c < C; ++c) racc[c] = sracc[c * kTile + j];
+                for (int c = 0; c < C; ++c) facc[c] = racc[c] = T(0);
                 SymSteps<Sym, T, 0>::run(tr, src, facc, racc);
+                // 16 terms of each sum in T, then into the double sums
 #pragma unroll
-                for (int c = 0; c < C; ++c) sracc[c * kTile + j] = racc[c];
+                for (int c = 0; c < C; ++c) {
+                    acc[c] += (double)facc[c];
+                    sracc[c * kTile + j] += (double)racc[c];
+                }
             }
             __syncthreads();  // each quarter's reverse sums go to the wave that takes it next
         }
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            acc[c] += (double)facc[c];
-            rev[((int64_t)p * C + c) * kTile + tid] = sracc[c * kTile + tid];
-        }
+        for (int c = 0; c < C; ++c) rev[((int64_t)p * C + c) * kTile + tid] = T(sracc[c * kTile + tid]);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) sa.fwd[((int64_t)blk * C + c) * kTile + tid] = acc[c];

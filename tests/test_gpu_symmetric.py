@@ -6,8 +6,10 @@ halves its pair work this way), the near tile pairs as before.  Every layer
 kind in both precisions on the ellipsoid (1, .8, .6) and the four-atom
 molecule at h = 1/32 (many far tile pairs): within 1e-12 (FP64) and 3e-6
 (float pairs, raw double layer within its coordinate-rounding bound) of the
-oracle on every row, and within 1e-13 / 2e-6 of the one-direction GPU sums
-(the same pairs summed in another order).  A mixed and an FP64 coupled solve
+oracle on every row, and within 1e-13 / 3e-7 of the one-direction GPU sums
+(the same pairs summed in another order; with float pairs both add the terms
+in float blocks of 16 into double sums, so they differ by the rounding of
+those blocks, measured up to 4.4e-8).  A mixed and an FP64 coupled solve
 with the symmetric far field for the default pass kinds of a new plan and for
 all of them land on the one-direction solve's drag (1e-10) and fields (1e-8).
 """
@@ -62,7 +64,7 @@ def test_symmetric_layers_against_oracle_and_one_direction(sd, kind):
             if prec == "mixed" and name == "dl_raw":
                 tol = max(TOL32, 4 * EPS32 * np.max(np.abs(S.x)) / delta**2)
             assert el < tol and es < tol
-            tol_dir = 1e-13 if prec == "fp64" else 2e-6
+            tol_dir = 1e-13 if prec == "fp64" else 3e-7
             assert sl < tol_dir and ss < tol_dir
     plan.close()
 
