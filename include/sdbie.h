@@ -181,15 +181,14 @@ int64_t sdbie_plan_n(sdbie_plan plan);
  * rounding.  0: every ordered pair in its own pass.  Plans of more than 524288
  * nodes have no room for the symmetric lists and keep every pass
  * one-directional whatever the mask.  The default, SDBIE_SYM_DEFAULT, selects
- * the kinds that are faster symmetric on gfx950: all but the double Stokes
- * passes (those spend more on moving a double record between lanes than the
- * shared geometry saves).  ERR_ARG for a null plan or unknown bits. */
+ * every kind: each is at least as fast symmetric on gfx950.  ERR_ARG for a
+ * null plan or unknown bits. */
 #define SDBIE_SYM_LAPLACE 1
 #define SDBIE_SYM_STOKES 2
 #define SDBIE_SYM_LAPLACE_F64 4
 #define SDBIE_SYM_STOKES_F64 8
 #define SDBIE_SYM_ALL 15
-#define SDBIE_SYM_DEFAULT (SDBIE_SYM_LAPLACE | SDBIE_SYM_STOKES | SDBIE_SYM_LAPLACE_F64)
+#define SDBIE_SYM_DEFAULT (SDBIE_SYM_LAPLACE | SDBIE_SYM_STOKES | SDBIE_SYM_LAPLACE_F64 | SDBIE_SYM_STOKES_F64)
 int sdbie_plan_set_symmetric(sdbie_plan plan, int families);
 
 /* out = layer sum of `dens` (device, [n] for Laplace, [3][n] for Stokes, in

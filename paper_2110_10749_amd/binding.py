@@ -191,7 +191,7 @@ SYM_STOKES = 2
 SYM_LAPLACE_F64 = 4
 SYM_STOKES_F64 = 8
 SYM_ALL = 15
-SYM_DEFAULT = SYM_LAPLACE | SYM_STOKES | SYM_LAPLACE_F64
+SYM_DEFAULT = SYM_LAPLACE | SYM_STOKES | SYM_LAPLACE_F64 | SYM_STOKES_F64
 
 
 class Plan:
