@@ -21,8 +21,8 @@
 // them in a fixed order (no atomics: results are bitwise reproducible).
 //
 // Precision: T = double evaluates everything in double.  T = float evaluates
-// pair geometry, smoothing and kernel values in float; each tile's partial sum
-// is then added into double accumulators.
+// pair geometry, smoothing and kernel values in float; every 16 terms of a
+// lane's sum are then added into its double accumulator.
 //
 // Smoothing: for rho = r/delta below SDBIE_RHO_SERIES_* the factors are Taylor
 // series in rho^2 (the closed forms cancel there); between that and the far
@@ -1084,7 +1084,8 @@ __global__ __launch_bounds__(kEpiThreads) void epilogue(int64_t n, int nslots, c
 // hands the reverse one back to the source's lane through the inverse
 // rotation.  A wave meets its 64
 // targets with a quarter of the 256 sources per phase (4 row rotations of 16
-// steps); the quarters' reverse accumulators pass between the waves in LDS.
+// steps); the quarters' reverse sums pass between the waves in LDS, as double
+// sums to which each row rotation adds its 16 terms.
 // Forward sums of the target tile go to one slot per block, reverse sums of
 // the source tile to one slot per tile pair; the symmetric epilogue adds them
 // (and the near-field slots) in a fixed order.
