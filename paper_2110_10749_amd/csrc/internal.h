@@ -117,7 +117,7 @@ struct Plan {
     double* px = nullptr;   // [3][npad]
     double* pn = nullptr;   // [3][npad]
     double* pw = nullptr;   // [npad]
-    float* px32 = nullptr;  // [3][npad]
+    float* px32 = nullptr;  // [3][npad], each node minus the centre of its tile's box
     double* boxes = nullptr;   // [ntiles][6] min/max per axis
     double* uboxes = nullptr;  // [npad / kNearUnit][6]: the same per near-field unit of sources
     uint8_t* mask64 = nullptr; // [ntiles][ntiles]: 1 if the tile pair may hold a pair with rho < double cutoff

@@ -187,7 +187,8 @@ struct KArgs {
     const double* x;    // padded sorted coordinates [3][npad]
     const double* nrm;  // padded sorted normals [3][npad]
     const double* w;    // padded sorted weights [npad] (0 on padding)
-    const float* x32;   // padded sorted coordinates, float [3][npad]
+    const float* x32;   // padded sorted coordinates, float, in their tile's frame [3][npad]
+    const double* tboxes;  // [ntiles][6] tile boxes (min, max per axis); a tile's frame is its box centre
     const uint8_t* mask;  // [ntiles][ntiles] near-field tile pairs
     const double* dl_dens;  // sorted, stride n
     const double* sl_dens;  // sorted, stride n
@@ -208,6 +209,33 @@ struct KArgs {
 template <typename T> __device__ __forceinline__ T load_x(const KArgs& a, int c, int64_t j);
 template <> __device__ __forceinline__ double load_x<double>(const KArgs& a, int c, int64_t j) { return a.x[c * a.npad + j]; }
 template <> __device__ __forceinline__ float load_x<float>(const KArgs& a, int c, int64_t j) { return a.x32[c * a.npad + j]; }
+
+// Float coordinates are taken in the frame of a tile, the centre of its box: a
+// source's in its own tile's (the records), a target's moved into the frame of
+// each source tile it meets.  D = x_i - x_j is then formed from numbers about
+// as large as the distance to the source tile's centre, not to the body's, so
+// the float rounding of the coordinates (eps32 times their size) weighs less
+// on the close pairs.  Double coordinates stay absolute.
+__device__ __forceinline__ double tile_centre(const KArgs& a, int t, int c) {
+    return 0.5 * (a.tboxes[6 * t + 2 * c] + a.tboxes[6 * t + 2 * c + 1]);
+}
+template <typename T, class Op>
+__device__ __forceinline__ void own_frame(const Op& op, T (&x0)[3]) {
+    if constexpr (sizeof(T) == 4) {
+        x0[0] = op.xi;
+        x0[1] = op.yi;
+        x0[2] = op.zi;
+    }
+}
+// x0: the target's float coordinates in its own tile's frame (tile tt)
+template <typename T, class Op>
+__device__ __forceinline__ void targets_to_frame(Op& op, const KArgs& a, const T (&x0)[3], int tt, int t) {
+    if constexpr (sizeof(T) == 4) {
+        op.xi = x0[0] + (float)(tile_centre(a, tt, 0) - tile_centre(a, t, 0));
+        op.yi = x0[1] + (float)(tile_centre(a, tt, 1) - tile_centre(a, t, 1));
+        op.zi = x0[2] + (float)(tile_centre(a, tt, 2) - tile_centre(a, t, 2));
+    }
+}
 
 __device__ __forceinline__ double dens_at(const double* d, int64_t n, int c, int64_t j) {
     return j < n ? d[c * n + j] : 0.0;
@@ -780,6 +808,8 @@ __device__ __forceinline__ void far_body(const KArgs& a, int blk) {
     const int64_t i = (int64_t)b * kTPB + threadIdx.x;  // < npad
     Op op;
     op.init(a, i);
+    T x0[3] = {};
+    own_frame<T>(op, x0);
     const T id = T(a.inv_delta), id2 = id * id, rc2 = T(a.rc2);
     const int t0 = split * a.tiles_per_split;
     const int t1 = t0 + a.tiles_per_split < a.ntiles ? t0 + a.tiles_per_split : a.ntiles;
@@ -789,6 +819,7 @@ __device__ __forceinline__ void far_body(const KArgs& a, int blk) {
     static_assert(kTile % B == 0 && B % Op::U == 0, "blocks of whole unrolled steps");
     for (int t = t0; t < t1; ++t) {
         if (row[t]) continue;  // uniform
+        targets_to_frame<T>(op, a, x0, b, t);
         const src_ptr<T> rt = rec + (int64_t)t * kTile * Op::R;
 #pragma unroll 1
         for (int jb = 0; jb < kTile; jb += B) {
@@ -827,6 +858,8 @@ __device__ __forceinline__ void far_lds_body(const KArgs& a, int blk) {
     const int64_t i = (int64_t)b * kTPB + threadIdx.x;  // < npad
     Op op;
     op.init(a, i);
+    T x0[3] = {};
+    own_frame<T>(op, x0);
     const T id = T(a.inv_delta), id2 = id * id, rc2 = T(a.rc2);
     const int t0 = split * a.tiles_per_split;
     const int t1 = t0 + a.tiles_per_split < a.ntiles ? t0 + a.tiles_per_split : a.ntiles;
@@ -849,6 +882,7 @@ __device__ __forceinline__ void far_lds_body(const KArgs& a, int blk) {
         g = rec + (int64_t)(tn < t1 ? tn : t) * kTile * Q + threadIdx.x;
 #pragma unroll
         for (int c = 0; c < Q; ++c) pf[c] = g[c * kTPB];
+        targets_to_frame<T>(op, a, x0, b, t);
         constexpr int B = block_terms<T>();
         static_assert(kTile % B == 0 && B % Op::U == 0, "blocks of whole unrolled steps");
 #pragma unroll 1
@@ -901,6 +935,8 @@ __device__ __forceinline__ void near_body(const KArgs& a, int blk) {
     const int64_t i = (int64_t)b * kTPB + threadIdx.x;
     Op op;
     op.init(a, i);
+    T x0[3] = {};
+    own_frame<T>(op, x0);
     const T id = T(a.inv_delta), id2 = id * id, rc2 = T(a.rc2);
     // bounding box of the wave's 64 targets (equal in every lane)
     const int64_t w0 = (int64_t)b * kTPB + (threadIdx.x & ~63);
@@ -926,6 +962,7 @@ __device__ __forceinline__ void near_body(const KArgs& a, int blk) {
         while (bal) {
             const int t = c0 + __ffsll((long long)bal) - 1;
             bal &= bal - 1;
+            targets_to_frame<T>(op, a, x0, b, t);
             for (int q = 0; q < kUnits; ++q) {
                 if ((rank * kUnits + q) % a.nsplit != split) continue;
                 const int64_t u0 = (int64_t)t * kTile + q * kNearUnit;
@@ -1303,6 +1340,7 @@ __device__ __forceinline__ void sym_far_body(const KArgs& a, const SymArgs& sa, 
     T tr[R];
 #pragma unroll
     for (int f = 0; f < R; ++f) tr[f] = rec[((int64_t)ta * kTile + tid) * R + f];
+    const T x0[3] = {tr[0], tr[1], tr[2]};  // the targets in their own tile's frame
     double acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0;
@@ -1313,6 +1351,10 @@ __device__ __forceinline__ void sym_far_body(const KArgs& a, const SymArgs& sa, 
     src.l16 = lane & 15;
     for (int it = first; it < first + cnt; ++it) {
         const int tb = sa.items[3 * it + 1], p = sa.items[3 * it + 2];
+        if constexpr (sizeof(T) == 4) {  // the targets in the source tile's frame
+#pragma unroll
+            for (int c = 0; c < 3; ++c) tr[c] = x0[c] + (float)(tile_centre(a, ta, c) - tile_centre(a, tb, c));
+        }
         __syncthreads();  // the previous tile pair is done with the LDS
 #pragma unroll
         for (int f = 0; f < R; ++f) srec[f * kTile + tid] = rec[((int64_t)tb * kTile + tid) * R + f];
@@ -1407,6 +1449,7 @@ KArgs make_args(const Plan& P, const PassDesc& d, int nsplit, double cut) {
     a.nrm = P.pn;
     a.w = P.pw;
     a.x32 = P.px32;
+    a.tboxes = P.boxes;
     a.mask = d.mixed ? P.mask32 : P.mask64;
     a.dl_dens = d.dl_dens;
     a.sl_dens = d.sl_dens;

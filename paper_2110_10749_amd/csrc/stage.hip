@@ -116,7 +116,7 @@ __global__ void k_stage(int64_t n, const uint64_t* __restrict__ keys, const doub
 // its distance from the origin.
 __global__ void k_pad(int64_t n, int64_t npad, const double* __restrict__ xs, const double* __restrict__ ns,
                       const double* __restrict__ ws, const double* __restrict__ bb, double* __restrict__ px,
-                      double* __restrict__ pn, double* __restrict__ pw, float* __restrict__ px32) {
+                      double* __restrict__ pn, double* __restrict__ pw) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= npad) return;
     const double ext = fmax(fmax(bb[1] - bb[0], bb[3] - bb[2]), bb[5] - bb[4]);
@@ -124,9 +124,18 @@ __global__ void k_pad(int64_t n, int64_t npad, const double* __restrict__ xs, co
         const double xv = k < n ? xs[c * n + k] : bb[2 * c + 1] + 10.0 * ext + 1.0;
         px[c * npad + k] = xv;
         pn[c * npad + k] = k < n ? ns[c * n + k] : 0.0;
-        px32[c * npad + k] = (float)(xv - 0.5 * (bb[2 * c] + bb[2 * c + 1]));
     }
     pw[k] = k < n ? ws[k] : 0.0;
+}
+
+// float coordinates in the frame of their tile: minus the centre of the tile's
+// box (every tile holds at least one real node, so the centre is finite)
+__global__ void k_frame32(int64_t npad, const double* __restrict__ px, const double* __restrict__ boxes,
+                          float* __restrict__ px32) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= npad) return;
+    const double* b = boxes + (k / kTile) * 6;
+    for (int c = 0; c < 3; ++c) px32[c * npad + k] = (float)(px[c * npad + k] - 0.5 * (b[2 * c] + b[2 * c + 1]));
 }
 
 // bounding box of each group of W consecutive (sorted) real nodes (empty:
@@ -276,10 +285,13 @@ void stage_surface(Plan& P, const sdbie_surface* s, hipStream_t st) {
     SDBIE_LAUNCHED();
     hipLaunchKernelGGL(k_pad, dim3((unsigned)((P.npad + 255) / 256)), dim3(256), 0, st, n, P.npad,
                        (const double*)P.x, (const double*)P.nrm, (const double*)P.w, (const double*)bb, P.px, P.pn,
-                       P.pw, P.px32);
+                       P.pw);
     SDBIE_LAUNCHED();
     hipLaunchKernelGGL((k_boxes<kTile>), dim3((unsigned)P.ntiles), dim3(kTile), 0, st, n, (const double*)P.x,
                        P.boxes);
+    SDBIE_LAUNCHED();
+    hipLaunchKernelGGL(k_frame32, dim3((unsigned)((P.npad + 255) / 256)), dim3(256), 0, st, P.npad,
+                       (const double*)P.px, (const double*)P.boxes, P.px32);
     SDBIE_LAUNCHED();
     hipLaunchKernelGGL((k_boxes<kNearUnit>), dim3((unsigned)(P.npad / kNearUnit)), dim3(kNearUnit), 0, st, n,
                        (const double*)P.x, P.uboxes);
