@@ -10,9 +10,10 @@
 // over the next power of two (padding keys = UINT64_MAX; keys are unique, so
 // the order is deterministic), then gather of x, n, w into sorted double
 // arrays and the weighted normals w n; copies padded to whole tiles of kTile
-// nodes (double and float) for the pair kernels; per-tile bounding boxes and
-// the near-field masks of tile pairs (box distance below rho_cut delta, one
-// mask for the double cutoff and one for the float cutoff).
+// nodes for the pair kernels; per-tile bounding boxes; a float copy of the
+// coordinates in the frame of each node's tile; and the near-field masks of
+// tile pairs (box distance below rho_cut delta, one mask for the double cutoff
+// and one for the float cutoff).
 #include <vector>
 
 #include "smoothing_coeffs.h"
@@ -110,10 +111,6 @@ __global__ void k_stage(int64_t n, const uint64_t* __restrict__ keys, const doub
 
 // padded copies for the pair kernels: nodes k >= n sit at a point `far`
 // outside the bounding box (10 extents away) with zero weight and normal.
-// The float copy is taken relative to the centre of the bounding box: the
-// kernels see coordinates only through differences x_i - x_j, and the
-// rounding of a float coordinate is then set by the body's extent, not by
-// its distance from the origin.
 __global__ void k_pad(int64_t n, int64_t npad, const double* __restrict__ xs, const double* __restrict__ ns,
                       const double* __restrict__ ws, const double* __restrict__ bb, double* __restrict__ px,
                       double* __restrict__ pn, double* __restrict__ pw) {
@@ -129,7 +126,11 @@ __global__ void k_pad(int64_t n, int64_t npad, const double* __restrict__ xs, co
 }
 
 // float coordinates in the frame of their tile: minus the centre of the tile's
-// box (every tile holds at least one real node, so the centre is finite)
+// box (every tile holds at least one real node, so the centre is finite).  The
+// kernels see coordinates only through differences x_i - x_j, formed after
+// moving the targets into the source tile's frame, so the rounding of a float
+// coordinate is set by the tile's extent, not by the body's or by the
+// distance from the origin.
 __global__ void k_frame32(int64_t npad, const double* __restrict__ px, const double* __restrict__ boxes,
                           float* __restrict__ px32) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
