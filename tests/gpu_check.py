@@ -18,6 +18,20 @@ EPS32 = 2.0**-24
 LAYERS = [("sl", O.LSL, O.SSL), ("dl_raw", O.LDL, O.SDL), ("dl_sub", O.LDLS, O.SDLS)]
 
 
+# Float pairs at h = 1/64 (delta = 3/64): the coordinates enter D in the frame of
+# the source tile, so a close pair's D carries eps32 times its distance from that
+# tile's centre (at most about two tile extents, 0.5 on these surfaces) and the
+# single and subtracted double layers stay within 4 eps32 * 0.5 / delta ~ 1.1e-6
+# of the largest output; the bar adds a margin (measured up to 6.6e-7).
+TOL32_TILE_FRAMES_H64 = 1.5e-6
+
+
+def assert_tile_frame_bound(out):
+    for name in ("sl", "dl_sub"):
+        el, es = out[(name, "mixed")]
+        assert max(el, es) < TOL32_TILE_FRAMES_H64, (name, el, es)
+
+
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
 

@@ -29,7 +29,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_check import check_all_layers, dev
+from gpu_check import assert_tile_frame_bound, check_all_layers, dev
 from oracle import oracle as O
 from workloads import exact, fields, surfaces
 
@@ -139,7 +139,8 @@ def test_layers_sampled_rows(sd, kind):
     S = make_surface(kind, 1.0 / 64)
     rng = np.random.default_rng(21)
     t = np.sort(rng.choice(S.N, size=192, replace=False))
-    check_all_layers(sd, S.x, S.n, S.w, 3.0 / 64, seed=22, targets=t)
+    out = check_all_layers(sd, S.x, S.n, S.w, 3.0 / 64, seed=22, targets=t)
+    assert_tile_frame_bound(out)
 
 
 def test_layers_molecule_all_rows(sd):

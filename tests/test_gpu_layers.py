@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_check import TOL32, check_all_layers, dev, make_plan, relerr
+from gpu_check import TOL32, assert_tile_frame_bound, check_all_layers, dev, make_plan, relerr
 from oracle import oracle as O
 from workloads import fields, surfaces
 
@@ -65,7 +65,8 @@ def test_large_sampled_rows(sd):
     S = surfaces.sphere(1.0 / 64)
     rng = np.random.default_rng(7)
     t = np.sort(rng.choice(S.N, size=256, replace=False))
-    check_all_layers(sd, S.x, S.n, S.w, 3.0 / 64, seed=14, targets=t)
+    out = check_all_layers(sd, S.x, S.n, S.w, 3.0 / 64, seed=14, targets=t)
+    assert_tile_frame_bound(out)
 
 
 def test_mixed_error_bound_on_smooth_densities(sd):
